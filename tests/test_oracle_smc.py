@@ -1,0 +1,201 @@
+"""Pins of the oracle's SMC stage machinery: tolerance (eq. 8), prior set
+and resampling weights (eqs. 9-10), categorical draw (eq. 11), importance
+weights, and end-to-end behaviour of a run."""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_2106_15508_amd import workloads as W
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 64, 1000, 1023, 4096])
+@pytest.mark.parametrize("alpha", [0.5, 0.1, 0.25, 0.9, 0.3333])
+def test_quantile_bitwise_numpy_linear(oracle, n, alpha):
+    rng = np.random.default_rng(n * 7 + int(alpha * 1000))
+    for x in (rng.exponential(1e5, n), np.round(rng.uniform(0, 50, n)), rng.uniform(size=n)):
+        want = np.quantile(x, alpha, method="linear")
+        assert oracle.quantile(x, alpha) == want
+
+
+def test_resample_weights_properties(oracle):
+    rng = np.random.default_rng(3)
+    d = rng.exponential(1.0, 500)
+    eps = float(np.median(d))
+    q, Cc, ns = oracle.resample_weights(d, eps)
+    surv = d < eps
+    assert ns == surv.sum()
+    assert np.all(q[~surv] == 0)
+    w = eps - d
+    wmax = w[surv].max()
+    # q_k = floor(2^40 w_k / w_max): within one unit of the exact scaled weight
+    exact = w[surv] / wmax * 2.0**40
+    assert np.all(np.abs(q[surv].astype(np.float64) - exact) < 1.0 + 1e-3)
+    assert q.max() == 2**40
+    assert np.array_equal(Cc, np.cumsum(q.astype(object)).astype(np.uint64))
+
+
+def test_resample_weights_fallbacks(oracle):
+    d = np.array([3.0, 3.0, 5.0, 3.0])
+    q, Cc, ns = oracle.resample_weights(d, 3.0)   # nothing strictly below: use <=
+    assert ns == 3
+    assert list(q) == [1, 1, 0, 1]          # all survivors at w = 0: equal weights
+    assert list(Cc) == [1, 2, 2, 3]
+
+
+def test_parent_draw_boundaries(oracle):
+    """r = floor(R Q / 2^64); parent = first k with C_k > r.  Words that
+    land exactly on r = C_{k-1} and r = C_k - 1 select particle k."""
+    q = np.array([5, 0, 3, 1, 0, 7, 2**40, 0, 9], dtype=np.uint64)
+    Cc = np.cumsum(q).astype(np.uint64)
+    Q = int(Cc[-1])
+    prev = 0
+    for k, ck in enumerate(Cc):
+        ck = int(ck)
+        if q[k] == 0:
+            continue
+        for r in (prev, ck - 1):
+            R = -(-(r << 64) // Q)  # smallest R with floor(R Q / 2^64) = r
+            assert (R * Q) >> 64 == r
+            assert oracle.parent(Cc, R) == k
+        prev = ck
+
+
+def test_parent_frequencies(oracle):
+    rng = np.random.default_rng(4)
+    q = rng.integers(0, 1000, 40).astype(np.uint64)
+    q[::7] = 0
+    Cc = np.cumsum(q).astype(np.uint64)
+    cnt = 100000
+    Rs = rng.integers(0, 2**64, cnt, dtype=np.uint64)
+    ks = np.array([oracle.parent(Cc, int(R)) for R in Rs])
+    obs = np.bincount(ks, minlength=q.size)
+    assert np.all(obs[q == 0] == 0)
+    p = q.astype(np.float64) / q.sum()
+    keep = q > 0
+    assert stats.chisquare(obs[keep], p[keep] * cnt).pvalue > 1e-3
+
+
+def _mp_log_weight(u_j, s, u_prev, q):
+    mpmath.mp.dps = 50
+    L = mpmath.mpf(0)
+    for k in range(len(q)):
+        if q[k] == 0:
+            continue
+        D = sum((mpmath.mpf(float(u_j[d])) - mpmath.mpf(float(u_prev[k][d]))) ** 2 for d in range(8))
+        L += int(q[k]) * mpmath.exp(-D / (2 * mpmath.mpf(float(s)) ** 2))
+    return 8 * mpmath.log(mpmath.mpf(float(s))) - mpmath.log(L)
+
+
+def test_log_weight_brute_force(oracle):
+    """Row sum of the importance weight against 50-digit arithmetic, N <= 8."""
+    rng = np.random.default_rng(5)
+    for trial in range(20):
+        M = int(rng.integers(1, 9))
+        u_prev = rng.uniform(size=(M, 8))
+        q = rng.integers(0, 2**40, M).astype(np.uint64)
+        q[0] = max(int(q[0]), 1)
+        if M > 2:
+            q[1] = 0
+        s = float(10 ** rng.uniform(-3, -0.3))
+        u_j = np.clip(u_prev[0] + s * rng.standard_normal(8), 0, 1)
+        got = oracle.log_weight(u_j, s, u_prev, q)
+        want = _mp_log_weight(u_j, s, u_prev, q)
+        assert abs(got - float(want)) <= 1e-13 * max(1.0, abs(float(want)))
+
+
+def test_log_weight_is_gaussian_mixture_density(oracle):
+    """With equal q_k the weight is the reciprocal of an equal-weight
+    Gaussian mixture density (scipy.stats.multivariate_normal)."""
+    rng = np.random.default_rng(6)
+    M, s = 6, 0.2
+    u_prev = rng.uniform(size=(M, 8))
+    q = np.full(M, 1000, dtype=np.uint64)
+    for _ in range(5):
+        u_j = rng.uniform(size=8)
+        dens = np.mean([stats.multivariate_normal(u_prev[k], s * s * np.eye(8)).pdf(u_j) for k in range(M)])
+        # l = 8 log s - log sum_k q exp(...) = -log(dens) - 4 log(2 pi) - log(q M)
+        want = -math.log(dens) - 4 * math.log(2 * math.pi) - math.log(1000 * M)
+        assert abs(oracle.log_weight(u_j, s, u_prev, q) - want) < 1e-9 * abs(want) + 1e-9
+
+
+def test_normalise(oracle):
+    rng = np.random.default_rng(7)
+    l = rng.normal(0, 30, 5000)
+    Wn, ess = oracle.normalise(l)
+    assert abs(Wn.sum() - 1) < 1e-14
+    assert np.all(Wn >= 0)
+    want = np.exp(l - l.max()) / np.exp(l - l.max()).sum()
+    np.testing.assert_allclose(Wn, want, rtol=1e-12, atol=1e-300)
+    assert abs(ess - 1 / np.sum(want**2)) < 1e-9 * ess
+
+
+# ----------------------------------------------------------------- runs
+
+@pytest.fixture(scope="module")
+def c1_run(oracle):
+    w = W.C1.with_(n_rounds=10, step_schedule=W.STEP_PAPER)
+    obs = oracle.observations(w)
+    return w, obs, oracle.run(w, obs)
+
+
+def test_run_invariants(oracle, c1_run):
+    w, obs, r = c1_run
+    assert r.rc == 0
+    N = w.n_particles
+    assert np.all(np.diff(r.eps_next) <= 0)            # eq. 8: non-increasing
+    for i in range(1, w.n_rounds):
+        assert np.all(r.dist[i] <= r.eps[i])            # accepted only if d <= eps
+        assert np.all(np.diff(r.index[i]) > 0)          # first N in proposal order
+        assert r.proposals[i] == r.index[i][-1] + 1
+        assert np.all((r.u[i] >= 0) & (r.u[i] <= 1))
+        assert abs(r.W[i].sum() - 1) < 1e-13
+        assert r.beta_b[i] == 2 * i and r.beta_a[i] == r.eps[i] / r.eps[1]   # eq. 16
+        assert np.all(r.sigma[i] >= 1e-8)
+    assert r.beta_a[1] == 1.0 and r.beta_b[1] == 2   # Beta(1,2) in the first stage
+    assert np.all(r.W[0] == 1.0 / N)
+    # the accepted particles re-simulate to the same distance
+    for i in (0, 3, 9):
+        for k in (0, N // 2, N - 1):
+            d = oracle.sim_distance(w, obs, r.u[i][k], i, int(r.index[i][k]))
+            assert d == r.dist[i][k]
+
+
+def test_run_reproduces_proposals(oracle, c1_run):
+    """Each accepted particle of stage i is the proposal its index draws
+    from the stage's own resampling law (eqs. 9-11, 16-17)."""
+    w, obs, r = c1_run
+    for i in (1, 5):
+        q, Cc, _ = oracle.resample_weights(r.dist[i - 1], r.eps[i])
+        for k in (0, 7, w.n_particles - 1):
+            a, u, s, par = oracle.perturb(w, i, int(r.index[i][k]), r.u[i - 1], Cc,
+                                          r.beta_a[i], int(r.beta_b[i]))
+            assert a == r.attempts[i][k] and s == r.sigma[i][k] and par == r.parent[i][k]
+            assert np.array_equal(u, r.u[i][k])
+
+
+def test_posterior_recovery(oracle, c1_run):
+    """After 10 stages the population concentrates around the generating
+    values of the identifiable parameters alpha0, beta, gamma, delta, eta."""
+    w, obs, r = c1_run
+    th = r.theta(w)[-1]
+    width = np.asarray(w.hi) - np.asarray(w.lo)
+    for p in (0, 3, 4, 5, 6):
+        med = np.median(th[:, p])
+        assert abs(med - W.THETA_TRUE[p]) < 0.05 * width[p], (W.PARAM_NAMES[p], med)
+        wm = float((r.W[-1] * th[:, p]).sum())
+        assert abs(wm - W.THETA_TRUE[p]) < 0.08 * width[p], (W.PARAM_NAMES[p], wm)
+    assert r.eps_next[-1] < 0.2 * r.eps_next[0]
+
+
+def test_bdss_beats_fixed_step(oracle):
+    """The eq. 16 schedule reaches a lower tolerance than a fixed Beta(2,5)
+    step law in the same number of stages (the paper's central claim,
+    §IV-A, on the synthetic series)."""
+    w = W.C1.with_(n_rounds=7)
+    obs = oracle.observations(w)
+    paper = oracle.run(w.with_(step_schedule=W.STEP_PAPER), obs)
+    fixed = oracle.run(w.with_(step_schedule=W.STEP_FIXED), obs)
+    assert paper.eps_next[-1] < fixed.eps_next[-1]

@@ -1,0 +1,265 @@
+"""Python binding of the HIP library (``libabcsmc_hip.so``, C ABI in
+``include/abcsmc.h``).
+
+Argument marshalling only: every step of the method runs in the library's
+kernels.  PyTorch, when used, supplies device memory (a workspace tensor) and
+the stream; it is optional.  Loading fails loudly when the library is
+missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libabcsmc_hip.so")
+
+ABI_VERSION = 1
+OK, EINVAL, ENOMEM, EDEVICE, EBUDGET, ESTATE, EDEGENERATE = 0, -1, -2, -3, -4, -5, -6
+F_EARLY_EXIT = 1
+F_STEP_IS_VARIANCE = 2
+
+#: every function the header declares
+EXPORTS = (
+    "abcsmc_workspace_size", "abcsmc_init", "abcsmc_round", "abcsmc_weights", "abcsmc_population",
+    "abcsmc_resampling", "abcsmc_rounds_done", "abcsmc_run", "abcsmc_simulate", "abcsmc_debug_eval",
+    "abcsmc_free", "abcsmc_strerror", "abcsmc_last_error", "abcsmc_abi_version",
+)
+
+
+class AbcsmcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"abcsmc error {code}: {msg}")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_int32), ("n_params", C.c_int32),
+        ("prior_lo", C.c_double * 8), ("prior_hi", C.c_double * 8),
+        ("population", C.c_int64), ("n_days", C.c_int32), ("n_particles", C.c_int64),
+        ("batch", C.c_int64), ("surv_ratio", C.c_double), ("step_schedule", C.c_int32),
+        ("beta_a", C.c_double), ("beta_b", C.c_int32), ("sampler", C.c_int32),
+        ("flags", C.c_int32), ("max_attempts", C.c_int32), ("seed", C.c_uint64),
+        ("max_proposals", C.c_int64), ("stream", C.c_void_p), ("workspace", C.c_void_p),
+        ("workspace_bytes", C.c_size_t),
+    ]
+
+
+class RoundInfo(C.Structure):
+    _fields_ = [
+        ("round", C.c_int32), ("beta_b", C.c_int32), ("eps", C.c_double), ("eps_next", C.c_double),
+        ("beta_a", C.c_double), ("ess", C.c_double), ("proposals", C.c_int64),
+        ("simulated", C.c_int64), ("invalid", C.c_int64), ("attempts", C.c_int64),
+        ("survivors", C.c_int64), ("batches", C.c_int64), ("ms_resample", C.c_double),
+        ("ms_simulate", C.c_double), ("ms_weights", C.c_double), ("ms_select", C.c_double),
+        ("ms_total", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: Optional[str] = None):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} (run python -m paper_2106_15508_amd.build)")
+    L = C.CDLL(path, mode=os.RTLD_LOCAL)
+    vp, i32, i64, u32, u64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
+    sig = {
+        "abcsmc_workspace_size": (C.c_int, [vp, vp]),
+        "abcsmc_init": (C.c_int, [vp, vp, vp]),
+        "abcsmc_round": (C.c_int, [vp, vp]),
+        "abcsmc_weights": (C.c_int, [vp, vp, vp, vp]),
+        "abcsmc_population": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+        "abcsmc_resampling": (C.c_int, [vp, vp, vp]),
+        "abcsmc_rounds_done": (C.c_int, [vp]),
+        "abcsmc_run": (C.c_int, [vp, vp, i32, vp, vp, vp, vp]),
+        "abcsmc_simulate": (C.c_int, [vp, i64, vp, vp, u64, u32, u32, vp]),
+        "abcsmc_debug_eval": (C.c_int, [i32, i64, vp, vp, d, i32]),
+        "abcsmc_free": (None, [vp]),
+        "abcsmc_strerror": (C.c_char_p, [C.c_int]),
+        "abcsmc_last_error": (C.c_char_p, [vp]),
+        "abcsmc_abi_version": (C.c_int, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    if L.abcsmc_abi_version() != ABI_VERSION:
+        raise RuntimeError("ABI version mismatch")
+    _lib = L
+    return L
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _check(rc: int, ctx=None):
+    if rc != OK:
+        L = load()
+        msg = L.abcsmc_last_error(ctx).decode()
+        raise AbcsmcError(rc, msg or L.abcsmc_strerror(rc).decode())
+
+
+def make_config(w: W.Workload, *, stream=None, workspace=None, flags: int = 0, **over) -> Config:
+    """abcsmc_config of a workload (plus field overrides)."""
+    w = w.with_(**over) if over else w
+    c = Config()
+    c.abi_version = ABI_VERSION
+    c.n_params = 8
+    c.prior_lo[:] = list(w.lo)
+    c.prior_hi[:] = list(w.hi)
+    c.population = w.population
+    c.n_days = w.n_days
+    c.n_particles = w.n_particles
+    c.batch = w.batch
+    c.surv_ratio = w.surv_ratio
+    c.step_schedule = w.step_schedule
+    c.beta_a = w.beta_a
+    c.beta_b = w.beta_b
+    c.sampler = w.sampler
+    c.flags = flags | (F_STEP_IS_VARIANCE if w.step_is_variance else 0)
+    c.max_attempts = w.max_attempts
+    c.seed = w.seed
+    c.max_proposals = w.max_proposals
+    c.stream = stream
+    if workspace is not None:
+        ptr, nbytes = workspace
+        c.workspace = ptr
+        c.workspace_bytes = nbytes
+    return c
+
+
+def workspace_size(w: W.Workload, **kw) -> int:
+    c = make_config(w, **kw)
+    n = C.c_size_t()
+    _check(load().abcsmc_workspace_size(C.byref(c), C.byref(n)))
+    return n.value
+
+
+def simulate(w: W.Workload, theta, seed: int, rnd: int, index0: int = 0, obs0=None, **over) -> np.ndarray:
+    """Trajectories (n, T+1, 6) of parameter vectors theta (n, 8) on the GPU."""
+    c = make_config(w, **over)
+    th = np.ascontiguousarray(np.atleast_2d(theta), dtype=np.float64)
+    n = th.shape[0]
+    o0 = np.ascontiguousarray(obs0 if obs0 is not None else w.obs0, dtype=np.int64)
+    traj = np.zeros((n, c.n_days + 1, 6), dtype=np.int64)
+    _check(load().abcsmc_simulate(C.byref(c), n, _p(th), _p(o0), seed, rnd, index0, _p(traj)))
+    return traj
+
+
+def observations(w: W.Workload, **over) -> np.ndarray:
+    """Synthetic observed series (T+1, 3) from the generating vector, on the GPU."""
+    traj = simulate(w, np.asarray(w.theta_true)[None], w.obs_seed, W.OBS_ROUND, 0, **over)
+    return np.ascontiguousarray(traj[0, :, 2:5])
+
+
+def debug_eval(fn: int, inp: np.ndarray, n: int, out: np.ndarray, pa: float = 0.0, pb: int = 0) -> np.ndarray:
+    inp = np.ascontiguousarray(inp)
+    _check(load().abcsmc_debug_eval(fn, n, _p(inp), _p(out), pa, pb))
+    return out
+
+
+class Context:
+    """One ABC-SMC run on the GPU (abcsmc_init ... abcsmc_free)."""
+
+    def __init__(self, w: W.Workload, obs, *, stream=None, workspace=None, flags: int = 0, **over):
+        self.w = w.with_(**over) if over else w
+        self.cfg = make_config(self.w, stream=stream, workspace=workspace, flags=flags)
+        self.obs = np.ascontiguousarray(obs, dtype=np.int64)
+        self._h = C.c_void_p()
+        self.L = load()
+        _check(self.L.abcsmc_init(C.byref(self.cfg), _p(self.obs), C.byref(self._h)))
+        self.infos: List[dict] = []
+
+    @property
+    def N(self) -> int:
+        return self.w.n_particles
+
+    def round(self) -> dict:
+        info = RoundInfo()
+        _check(self.L.abcsmc_round(self._h, C.byref(info)), self._h)
+        d = info.as_dict()
+        self.infos.append(d)
+        return d
+
+    def run(self, n_rounds: int) -> List[dict]:
+        return [self.round() for _ in range(n_rounds)]
+
+    def rounds_done(self) -> int:
+        return self.L.abcsmc_rounds_done(self._h)
+
+    def weights(self):
+        N = self.N
+        th, d, wt = np.zeros((N, 8)), np.zeros(N), np.zeros(N)
+        _check(self.L.abcsmc_weights(self._h, _p(th), _p(d), _p(wt)), self._h)
+        return th, d, wt
+
+    def population(self):
+        N = self.N
+        out = dict(u=np.zeros((N, 8)), sigma=np.zeros(N), parent=np.zeros(N, np.int64),
+                   index=np.zeros(N, np.int64), attempts=np.zeros(N, np.int32), logw=np.zeros(N))
+        _check(self.L.abcsmc_population(self._h, *(_p(out[k]) for k in
+                                                    ("u", "sigma", "parent", "index", "attempts", "logw"))),
+               self._h)
+        return out
+
+    def resampling(self):
+        N = self.N
+        q, cdf = np.zeros(N, np.uint64), np.zeros(N, np.uint64)
+        _check(self.L.abcsmc_resampling(self._h, _p(q), _p(cdf)), self._h)
+        return q, cdf
+
+    def close(self):
+        if self._h:
+            self.L.abcsmc_free(self._h)
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run(w: W.Workload, obs, n_rounds: Optional[int] = None, **over):
+    """abcsmc_run: returns (theta, dist, weight, infos)."""
+    c = make_config(w, **over)
+    R = n_rounds or w.n_rounds
+    N = c.n_particles
+    obs = np.ascontiguousarray(obs, dtype=np.int64)
+    th, d, wt = np.zeros((N, 8)), np.zeros(N), np.zeros(N)
+    infos = (RoundInfo * R)()
+    _check(load().abcsmc_run(C.byref(c), _p(obs), R, _p(th), _p(d), _p(wt), infos))
+    return th, d, wt, [i.as_dict() for i in infos]
+
+
+def torch_workspace(w: W.Workload, device: str = "cuda", **kw):
+    """A torch uint8 tensor big enough for the context's workspace, plus the
+    (pointer, bytes) pair the config takes."""
+    import torch
+    nbytes = workspace_size(w, **kw)
+    t = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    ptr = (t.data_ptr() + 255) // 256 * 256
+    return t, (ptr, nbytes)

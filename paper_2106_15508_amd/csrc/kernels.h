@@ -1,0 +1,145 @@
+// kernels.h -- kernel argument blocks and launch wrappers of the HIP path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace abcsmc {
+
+constexpr int kNP = 8;        // parameters per particle (eq. 1)
+constexpr int kBlock = 256;   // threads per workgroup of the per-lane kernels
+constexpr int kWave = 64;
+
+// Model constants shared by every simulation (§II-B).
+struct Model {
+    double lo[kNP];     // prior box lower corner
+    double width[kNP];  // hi - lo
+    double P;           // population (exact integer)
+    double invP;        // 1 / P
+    double A0, R0, D0;  // day-0 observed state
+    int32_t T;          // days
+    int32_t sampler;    // 0 binomial, 1 floor-normal
+    uint64_t seed;
+};
+
+// Device counters of one stage (8-byte words).
+struct StageCounters {
+    unsigned long long accepted;   // acceptances over the batches run so far
+    unsigned long long proposals;  // index of the N-th acceptance + 1 (0 until reached)
+    unsigned long long invalid;    // void proposals over the batches run so far
+    unsigned long long attempts;   // perturbation attempts over the batches run so far
+    unsigned long long base_rank;  // acceptances before the current batch
+    unsigned long long survivors;  // previous particles with q > 0
+    unsigned long long fallback;   // 1 if the prior set used d <= eps (no d < eps)
+    unsigned long long pad;
+};
+
+// Population of one stage, array-of-structures for the per-particle gathers.
+struct Population {
+    double* u;        // N x 8
+    double* d;        // N
+    double* sigma;    // N
+    int32_t* parent;  // N
+    uint32_t* index;  // N
+    int32_t* att;     // N
+    double* logw;     // N
+    double* W;        // N
+};
+
+struct ProposeArgs {
+    Model m;
+    const double* obs;  // (T+1) x 3, exact integers
+    uint32_t round;
+    uint32_t base;      // first proposal index of the batch
+    uint32_t count;     // proposals in the batch
+    int32_t max_attempts;
+    double eps;         // accept iff d <= eps
+    double exit_thr;    // early exit once the partial sum of squares exceeds this (+inf: off)
+    // perturbation (stage >= 1)
+    const double* u_prev;    // n_prev x 8
+    const uint64_t* cdf;     // n_prev inclusive prefix sums of q
+    int32_t n_prev;
+    double beta_a;
+    int32_t beta_b;
+    int32_t step_is_variance;
+    // staging, indexed by p = j - base
+    double* st_u;            // count x 8
+    double* st_d;
+    double* st_sigma;
+    int32_t* st_parent;
+    int32_t* st_att;
+    unsigned long long* wave_mask;  // ceil(count/64) acceptance ballots
+    StageCounters* ctr;
+};
+
+struct CompactArgs {
+    uint32_t base;
+    uint32_t count;
+    int32_t N;
+    const unsigned long long* wave_mask;
+    uint32_t* wave_off;   // exclusive prefix of popcounts
+    const double* st_u;
+    const double* st_d;
+    const double* st_sigma;
+    const int32_t* st_parent;
+    const int32_t* st_att;
+    Population pop;
+    StageCounters* ctr;
+};
+
+struct ResampleArgs {
+    const double* d_prev;   // N
+    const double* u_prev;   // N x 8
+    int32_t N;
+    double eps;
+    uint64_t* q;            // N
+    uint64_t* cdf;          // N
+    double* cols;           // M x 9: u_k[8], q_k  (q_k > 0 only, index order)
+    StageCounters* ctr;
+};
+
+struct WeightArgs {
+    const double* u;        // N x 8 rows
+    const double* sigma;    // N
+    const double* cols;     // M x 9
+    int32_t N;
+    const unsigned long long* M;  // device scalar: survivors
+    double* logw;           // N
+};
+
+struct NormArgs {
+    const double* logw;
+    double* W;
+    int32_t N;
+    double* ess;            // device scalar
+};
+
+struct SelectArgs {
+    const double* x;        // N non-negative (or +inf) values
+    int32_t N;
+    double alpha;
+    double* out;            // device scalar: type-7 quantile
+};
+
+struct TrajArgs {
+    Model m;
+    const double* theta;    // n x 8 (prior units)
+    int64_t n;
+    uint32_t round;
+    uint32_t index0;
+    int64_t* traj;          // n x (T+1) x 6
+};
+
+void launch_propose(const ProposeArgs& a, bool round0, hipStream_t s);
+void launch_compact(const CompactArgs& a, hipStream_t s);
+void launch_resample(const ResampleArgs& a, hipStream_t s);
+void launch_weights(const WeightArgs& a, hipStream_t s);
+void launch_normalise(const NormArgs& a, hipStream_t s);
+void launch_select(const SelectArgs& a, hipStream_t s);
+void launch_uniform_weights(double* W, double* logw, int32_t N, hipStream_t s);
+void launch_simulate_traj(const TrajArgs& a, hipStream_t s);
+void launch_to_theta(const double* u, const Model& m, double* theta, int64_t n, hipStream_t s);
+void launch_debug_eval(int32_t fn, int64_t n, const void* in, void* out, double pa, int32_t pb,
+                       hipStream_t s);
+
+}  // namespace abcsmc

@@ -1,0 +1,639 @@
+// runtime.hip -- host runtime behind the C ABI of include/abcsmc.h: config
+// validation, device workspace, the stage loop (resample -> batches of
+// proposals -> ordered compaction -> importance weights -> next tolerance)
+// and the copy-out calls.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "abcsmc.h"
+#include "kernels.h"
+
+using namespace abcsmc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct DevPop {
+    double* u;
+    double* d;
+    double* sigma;
+    int32_t* parent;
+    uint32_t* index;
+    int32_t* att;
+    double* logw;
+    double* W;
+    Population view() const { return Population{u, d, sigma, parent, index, att, logw, W}; }
+};
+
+// Byte layout of the device workspace (every region 256-byte aligned).
+struct Layout {
+    size_t obs, pop[2][8], q, cdf, cols, st_u, st_d, st_sigma, st_parent, st_att, wave_mask, wave_off,
+        ctr, scal, theta, total;
+};
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int64_t default_batch_cap(int64_t N)
+{
+    int64_t b = 4 * N;
+    if (b < 65536) b = 65536;
+    if (b > (int64_t)1 << 22) b = (int64_t)1 << 22;
+    return b;
+}
+
+int64_t batch_cap(const abcsmc_config& c)
+{
+    const int64_t b = c.batch > 0 ? c.batch : default_batch_cap(c.n_particles);
+    return (b + kBlock - 1) / kBlock * kBlock;
+}
+
+Layout make_layout(const abcsmc_config& c)
+{
+    Layout L{};
+    const size_t N = (size_t)c.n_particles, T = (size_t)c.n_days;
+    const size_t B = (size_t)batch_cap(c);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.obs = take((T + 1) * 3 * sizeof(double));
+    for (int p = 0; p < 2; ++p) {
+        L.pop[p][0] = take(N * kNP * sizeof(double));
+        L.pop[p][1] = take(N * sizeof(double));
+        L.pop[p][2] = take(N * sizeof(double));
+        L.pop[p][3] = take(N * sizeof(int32_t));
+        L.pop[p][4] = take(N * sizeof(uint32_t));
+        L.pop[p][5] = take(N * sizeof(int32_t));
+        L.pop[p][6] = take(N * sizeof(double));
+        L.pop[p][7] = take(N * sizeof(double));
+    }
+    L.q = take(N * sizeof(uint64_t));
+    L.cdf = take(N * sizeof(uint64_t));
+    L.cols = take(N * 9 * sizeof(double));
+    L.st_u = take(B * kNP * sizeof(double));
+    L.st_d = take(B * sizeof(double));
+    L.st_sigma = take(B * sizeof(double));
+    L.st_parent = take(B * sizeof(int32_t));
+    L.st_att = take(B * sizeof(int32_t));
+    L.wave_mask = take((B / kWave + 4) * sizeof(unsigned long long));
+    L.wave_off = take((B / kWave + 4) * sizeof(uint32_t));
+    L.ctr = take(sizeof(StageCounters));
+    L.scal = take(8 * sizeof(double));
+    L.theta = take(N * kNP * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+int fail(std::string* where, int code, const std::string& msg)
+{
+    if (where) *where = msg;
+    g_last_error = msg;
+    return code;
+}
+
+int validate(const abcsmc_config* c, const int64_t* obs, std::string* err)
+{
+    if (!c) return fail(err, ABCSMC_EINVAL, "config is NULL");
+    if (c->abi_version != ABCSMC_ABI_VERSION) return fail(err, ABCSMC_EINVAL, "abi_version mismatch");
+    if (c->n_params != ABCSMC_NPAR) return fail(err, ABCSMC_EINVAL, "n_params must be 8");
+    for (int d = 0; d < ABCSMC_NPAR; ++d)
+        if (!(c->prior_lo[d] <= c->prior_hi[d]) || !std::isfinite(c->prior_lo[d]) || !std::isfinite(c->prior_hi[d]))
+            return fail(err, ABCSMC_EINVAL, "prior box needs finite lo <= hi");
+    if (c->population < 1 || c->population >= ((int64_t)1 << 53)) return fail(err, ABCSMC_EINVAL, "population out of range");
+    if (c->n_days < 1 || c->n_days > 4096) return fail(err, ABCSMC_EINVAL, "n_days must be in [1, 4096]");
+    if (c->n_particles < 2 || c->n_particles > ((int64_t)1 << 22)) return fail(err, ABCSMC_EINVAL, "n_particles must be in [2, 2^22]");
+    if (c->batch < 0 || c->batch > ((int64_t)1 << 24)) return fail(err, ABCSMC_EINVAL, "batch must be in [0, 2^24]");
+    if (!(c->surv_ratio > 0.0 && c->surv_ratio < 1.0)) return fail(err, ABCSMC_EINVAL, "surv_ratio must be in (0,1)");
+    if (c->step_schedule != ABCSMC_STEP_PAPER && c->step_schedule != ABCSMC_STEP_FIXED)
+        return fail(err, ABCSMC_EINVAL, "unknown step_schedule");
+    if (c->step_schedule == ABCSMC_STEP_FIXED && (!(c->beta_a > 0.0) || !std::isfinite(c->beta_a) || c->beta_b < 1 || c->beta_b > 64))
+        return fail(err, ABCSMC_EINVAL, "fixed Beta needs a > 0 and integer 1 <= b <= 64");
+    if (c->sampler != ABCSMC_SAMPLER_BINOMIAL && c->sampler != ABCSMC_SAMPLER_NORMAL_FLOOR)
+        return fail(err, ABCSMC_EINVAL, "unknown sampler");
+    if (c->flags & ~(ABCSMC_F_EARLY_EXIT | ABCSMC_F_STEP_IS_VARIANCE)) return fail(err, ABCSMC_EINVAL, "unknown flags");
+    if (c->max_attempts < 0 || c->max_attempts > 4096) return fail(err, ABCSMC_EINVAL, "max_attempts must be in [0, 4096]");
+    if (c->max_proposals < 0) return fail(err, ABCSMC_EINVAL, "max_proposals must be >= 0");
+    if (obs) {
+        for (int64_t t = 0; t <= c->n_days; ++t)
+            for (int k = 0; k < 3; ++k)
+                if (obs[t * 3 + k] < 0 || obs[t * 3 + k] > c->population)
+                    return fail(err, ABCSMC_EINVAL, "observations must be counts in [0, P]");
+        if (obs[0] + obs[1] + obs[2] > c->population) return fail(err, ABCSMC_EINVAL, "A0 + R0 + D0 exceeds P");
+    }
+    return ABCSMC_OK;
+}
+
+Model make_model(const abcsmc_config& c, const int64_t* obs0)
+{
+    Model m{};
+    for (int d = 0; d < kNP; ++d) {
+        m.lo[d] = c.prior_lo[d];
+        m.width[d] = c.prior_hi[d] - c.prior_lo[d];
+    }
+    m.P = (double)c.population;
+    m.invP = 1.0 / m.P;
+    m.A0 = (double)obs0[0];
+    m.R0 = (double)obs0[1];
+    m.D0 = (double)obs0[2];
+    m.T = c.n_days;
+    m.sampler = c.sampler;
+    m.seed = c.seed;
+    return m;
+}
+
+}  // namespace
+
+#define HIPCHK(ctx, expr)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            (ctx)->broken = true;                                                          \
+            return fail(&(ctx)->err, ABCSMC_EDEVICE,                                       \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                \
+        }                                                                                  \
+    } while (0)
+
+struct abcsmc_ctx {
+    abcsmc_config cfg{};
+    Model model{};
+    Layout L{};
+    std::vector<int64_t> obs;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char* ws = nullptr;
+    bool own_ws = false;
+    bool broken = false;
+    std::string err;
+    hipEvent_t ev[6] = {};
+    DevPop pop[2]{};
+    int cur = 0;                 // pop[cur] holds the last completed stage
+    int32_t rounds = 0;          // stages completed
+    double eps_next = INFINITY;  // eps of the next stage
+    double eps1 = INFINITY;      // eps of stage 1 (eq. 16 normaliser)
+    double last_rate = 0.5;      // acceptance rate of the last stage (batch sizing)
+    int64_t N = 0;
+    template <typename T>
+    T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace {
+
+void bind_pops(abcsmc_ctx* x)
+{
+    for (int p = 0; p < 2; ++p) {
+        x->pop[p].u = x->at<double>(x->L.pop[p][0]);
+        x->pop[p].d = x->at<double>(x->L.pop[p][1]);
+        x->pop[p].sigma = x->at<double>(x->L.pop[p][2]);
+        x->pop[p].parent = x->at<int32_t>(x->L.pop[p][3]);
+        x->pop[p].index = x->at<uint32_t>(x->L.pop[p][4]);
+        x->pop[p].att = x->at<int32_t>(x->L.pop[p][5]);
+        x->pop[p].logw = x->at<double>(x->L.pop[p][6]);
+        x->pop[p].W = x->at<double>(x->L.pop[p][7]);
+    }
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+    return ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+int abcsmc_abi_version(void) { return ABCSMC_ABI_VERSION; }
+
+const char* abcsmc_strerror(int code)
+{
+    switch (code) {
+    case ABCSMC_OK: return "ok";
+    case ABCSMC_EINVAL: return "invalid argument";
+    case ABCSMC_ENOMEM: return "out of device memory";
+    case ABCSMC_EDEVICE: return "device error";
+    case ABCSMC_EBUDGET: return "proposal budget exhausted";
+    case ABCSMC_ESTATE: return "invalid state";
+    case ABCSMC_EDEGENERATE: return "degenerate population";
+    default: return "unknown error";
+    }
+}
+
+const char* abcsmc_last_error(const abcsmc_ctx* ctx)
+{
+    return ctx ? ctx->err.c_str() : g_last_error.c_str();
+}
+
+int abcsmc_workspace_size(const abcsmc_config* cfg, size_t* bytes)
+{
+    std::string e;
+    int rc = validate(cfg, nullptr, &e);
+    if (rc) return rc;
+    if (!bytes) return fail(nullptr, ABCSMC_EINVAL, "bytes is NULL");
+    *bytes = make_layout(*cfg).total;
+    return ABCSMC_OK;
+}
+
+void abcsmc_free(abcsmc_ctx* ctx)
+{
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (auto& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+int abcsmc_init(const abcsmc_config* cfg, const int64_t* obs, abcsmc_ctx** out)
+{
+    if (!out) return fail(nullptr, ABCSMC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!obs) return fail(nullptr, ABCSMC_EINVAL, "obs is NULL");
+    std::string e;
+    int rc = validate(cfg, obs, &e);
+    if (rc) return rc;
+    abcsmc_ctx* x = new abcsmc_ctx();
+    x->cfg = *cfg;
+    if (x->cfg.max_attempts == 0) x->cfg.max_attempts = 256;
+    x->N = cfg->n_particles;
+    const int64_t cap = ((int64_t)1 << 32) - 1 - batch_cap(*cfg);
+    if (x->cfg.max_proposals == 0 || x->cfg.max_proposals > cap)
+        x->cfg.max_proposals = std::min<int64_t>(cap, x->cfg.max_proposals ? x->cfg.max_proposals : 4096 * x->N);
+    x->obs.assign(obs, obs + (size_t)(cfg->n_days + 1) * 3);
+    x->model = make_model(x->cfg, obs);
+    x->L = make_layout(x->cfg);
+    auto bail = [&](int code) {
+        std::string msg = x->err;
+        abcsmc_free(x);
+        g_last_error = msg;
+        return code;
+    };
+    if (cfg->stream) {
+        x->stream = (hipStream_t)cfg->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&x->stream, hipStreamNonBlocking) != hipSuccess) {
+            x->err = "hipStreamCreate failed";
+            return bail(ABCSMC_EDEVICE);
+        }
+        x->own_stream = true;
+    }
+    if (cfg->workspace) {
+        if (cfg->workspace_bytes < x->L.total) {
+            x->err = "workspace too small";
+            return bail(ABCSMC_ENOMEM);
+        }
+        if (((uintptr_t)cfg->workspace) % kAlign) {
+            x->err = "workspace must be 256-byte aligned";
+            return bail(ABCSMC_EINVAL);
+        }
+        x->ws = (char*)cfg->workspace;
+    } else {
+        if (hipMalloc((void**)&x->ws, x->L.total) != hipSuccess) {
+            x->err = "hipMalloc of the workspace failed";
+            (void)hipGetLastError();
+            x->ws = nullptr;
+            return bail(ABCSMC_ENOMEM);
+        }
+        x->own_ws = true;
+    }
+    bind_pops(x);
+    for (auto& ev : x->ev)
+        if (hipEventCreate(&ev) != hipSuccess) {
+            x->err = "hipEventCreate failed";
+            return bail(ABCSMC_EDEVICE);
+        }
+    std::vector<double> od(x->obs.begin(), x->obs.end());
+    if (hipMemcpyAsync(x->at<double>(x->L.obs), od.data(), od.size() * sizeof(double), hipMemcpyHostToDevice,
+                       x->stream) != hipSuccess ||
+        hipStreamSynchronize(x->stream) != hipSuccess) {
+        x->err = "copy of the observations failed";
+        return bail(ABCSMC_EDEVICE);
+    }
+    *out = x;
+    return ABCSMC_OK;
+}
+
+int abcsmc_rounds_done(const abcsmc_ctx* ctx) { return ctx ? ctx->rounds : ABCSMC_EINVAL; }
+
+int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
+{
+    if (!x) return fail(nullptr, ABCSMC_EINVAL, "ctx is NULL");
+    if (x->broken) return fail(&x->err, ABCSMC_ESTATE, "context unusable after a device error");
+    const abcsmc_config& c = x->cfg;
+    const int32_t r = x->rounds;
+    const int N = (int)x->N;
+    const int nxt = x->rounds == 0 ? 0 : 1 - x->cur;  // buffer the new stage is written to
+    const DevPop& prev = x->pop[x->cur];
+    const DevPop& dst = x->pop[nxt];
+    StageCounters* ctr = x->at<StageCounters>(x->L.ctr);
+    double* scal = x->at<double>(x->L.scal);
+    hipStream_t s = x->stream;
+
+    const double eps = r == 0 ? INFINITY : x->eps_next;
+    double ba = 0.0;
+    int32_t bb = 0;
+    if (r > 0) {
+        if (c.step_schedule == ABCSMC_STEP_FIXED) {
+            ba = c.beta_a;
+            bb = c.beta_b;
+        } else {
+            const double e1 = r == 1 ? eps : x->eps1;
+            ba = eps / e1;  // eq. 16: alpha_i = eps_i / eps_1, beta_i = 2 i
+            bb = 2 * r;
+            if (bb > 128) return fail(&x->err, ABCSMC_EINVAL, "eq. 16 schedule limited to 64 stages");
+        }
+    }
+    const double exit_thr = ((c.flags & ABCSMC_F_EARLY_EXIT) && std::isfinite(eps))
+                                ? (eps * eps) * (1.0 + 0x1p-48)
+                                : INFINITY;
+
+    HIPCHK(x, hipMemsetAsync(ctr, 0, sizeof(StageCounters), s));
+    HIPCHK(x, hipEventRecord(x->ev[0], s));
+    if (r > 0) {
+        ResampleArgs ra{prev.d, prev.u, N, eps, x->at<uint64_t>(x->L.q), x->at<uint64_t>(x->L.cdf),
+                        x->at<double>(x->L.cols), ctr};
+        launch_resample(ra, s);
+        HIPCHK(x, hipGetLastError());
+    }
+    HIPCHK(x, hipEventRecord(x->ev[1], s));
+
+    ProposeArgs pa{};
+    pa.m = x->model;
+    pa.obs = x->at<double>(x->L.obs);
+    pa.round = (uint32_t)r;
+    pa.max_attempts = c.max_attempts;
+    pa.eps = eps;
+    pa.exit_thr = exit_thr;
+    pa.u_prev = prev.u;
+    pa.cdf = x->at<uint64_t>(x->L.cdf);
+    pa.n_prev = N;
+    pa.beta_a = ba;
+    pa.beta_b = bb;
+    pa.step_is_variance = (c.flags & ABCSMC_F_STEP_IS_VARIANCE) ? 1 : 0;
+    pa.st_u = x->at<double>(x->L.st_u);
+    pa.st_d = x->at<double>(x->L.st_d);
+    pa.st_sigma = x->at<double>(x->L.st_sigma);
+    pa.st_parent = x->at<int32_t>(x->L.st_parent);
+    pa.st_att = x->at<int32_t>(x->L.st_att);
+    pa.wave_mask = x->at<unsigned long long>(x->L.wave_mask);
+    pa.ctr = ctr;
+    CompactArgs ca{};
+    ca.N = N;
+    ca.wave_mask = pa.wave_mask;
+    ca.wave_off = x->at<uint32_t>(x->L.wave_off);
+    ca.st_u = pa.st_u;
+    ca.st_d = pa.st_d;
+    ca.st_sigma = pa.st_sigma;
+    ca.st_parent = pa.st_parent;
+    ca.st_att = pa.st_att;
+    ca.pop = dst.view();
+    ca.ctr = ctr;
+
+    const int64_t cap = batch_cap(c);
+    int64_t base = 0, batches = 0;
+    StageCounters hc{};
+    for (;;) {
+        int64_t B;
+        if (r == 0) {
+            B = std::min<int64_t>(cap, (int64_t)N - (int64_t)hc.accepted);
+        } else if (c.batch > 0) {
+            B = c.batch;
+        } else {
+            const double need = (double)(N - (int64_t)hc.accepted);
+            const double rate = x->last_rate > 1e-4 ? x->last_rate : 1e-4;
+            B = (int64_t)std::ceil(need / rate * 1.1) + 2048;
+            B = (B + kBlock - 1) / kBlock * kBlock;
+            if (B > cap) B = cap;
+        }
+        if (base + B > c.max_proposals) B = c.max_proposals - base;
+        if (B <= 0) return fail(&x->err, ABCSMC_EBUDGET, "stage exhausted its proposal budget");
+        pa.base = (uint32_t)base;
+        pa.count = (uint32_t)B;
+        launch_propose(pa, r == 0, s);
+        HIPCHK(x, hipGetLastError());
+        ca.base = pa.base;
+        ca.count = pa.count;
+        launch_compact(ca, s);
+        HIPCHK(x, hipGetLastError());
+        HIPCHK(x, hipMemcpyAsync(&hc, ctr, sizeof hc, hipMemcpyDeviceToHost, s));
+        HIPCHK(x, hipStreamSynchronize(s));
+        base += B;
+        ++batches;
+        if (hc.accepted >= (unsigned long long)N) break;
+        if (r > 0 && base > 0) x->last_rate = (double)hc.accepted / (double)base;
+    }
+    if (r > 0) x->last_rate = (double)N / (double)hc.proposals;
+    HIPCHK(x, hipEventRecord(x->ev[2], s));
+    if (r == 0) {
+        launch_uniform_weights(dst.W, dst.logw, N, s);
+    } else {
+        WeightArgs wa{dst.u, dst.sigma, x->at<double>(x->L.cols), N, &ctr->survivors, dst.logw};
+        launch_weights(wa, s);
+        HIPCHK(x, hipGetLastError());
+        NormArgs na{dst.logw, dst.W, N, scal + 1};
+        launch_normalise(na, s);
+    }
+    HIPCHK(x, hipGetLastError());
+    HIPCHK(x, hipEventRecord(x->ev[3], s));
+    SelectArgs sa{dst.d, N, c.surv_ratio, scal + 0};
+    launch_select(sa, s);
+    HIPCHK(x, hipGetLastError());
+    HIPCHK(x, hipEventRecord(x->ev[4], s));
+    double hs[2] = {0, 0};
+    HIPCHK(x, hipMemcpyAsync(hs, scal, sizeof hs, hipMemcpyDeviceToHost, s));
+    HIPCHK(x, hipStreamSynchronize(s));
+
+    // commit the stage
+    x->cur = nxt;
+    x->rounds = r + 1;
+    if (r == 1) x->eps1 = eps;
+    x->eps_next = hs[0];
+    if (info) {
+        abcsmc_round_info& I = *info;
+        std::memset(&I, 0, sizeof I);
+        I.round = r;
+        I.eps = eps;
+        I.eps_next = hs[0];
+        I.beta_a = ba;
+        I.beta_b = bb;
+        I.ess = r == 0 ? (double)N : hs[1];
+        I.proposals = (int64_t)hc.proposals;
+        I.simulated = base;
+        I.invalid = (int64_t)hc.invalid;
+        I.attempts = (int64_t)hc.attempts;
+        I.survivors = r == 0 ? 0 : (int64_t)hc.survivors;
+        I.batches = batches;
+        I.ms_resample = elapsed(x->ev[0], x->ev[1]);
+        I.ms_simulate = elapsed(x->ev[1], x->ev[2]);
+        I.ms_weights = elapsed(x->ev[2], x->ev[3]);
+        I.ms_select = elapsed(x->ev[3], x->ev[4]);
+        I.ms_total = elapsed(x->ev[0], x->ev[4]);
+    }
+    return ABCSMC_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int abcsmc_weights(const abcsmc_ctx* cx, double* theta, double* dist, double* weight)
+{
+    abcsmc_ctx* x = const_cast<abcsmc_ctx*>(cx);
+    if (!x) return fail(nullptr, ABCSMC_EINVAL, "ctx is NULL");
+    if (x->broken) return fail(&x->err, ABCSMC_ESTATE, "context unusable after a device error");
+    if (x->rounds == 0) return fail(&x->err, ABCSMC_ESTATE, "no completed stage");
+    const DevPop& p = x->pop[x->cur];
+    const size_t N = (size_t)x->N;
+    hipStream_t s = x->stream;
+    if (theta) {
+        double* th = x->at<double>(x->L.theta);
+        launch_to_theta(p.u, x->model, th, (int64_t)N, s);
+        HIPCHK(x, hipGetLastError());
+        HIPCHK(x, hipMemcpyAsync(theta, th, N * kNP * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    if (dist) HIPCHK(x, hipMemcpyAsync(dist, p.d, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (weight) HIPCHK(x, hipMemcpyAsync(weight, p.W, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(x, hipStreamSynchronize(s));
+    return ABCSMC_OK;
+}
+
+int abcsmc_population(const abcsmc_ctx* cx, double* u, double* sigma, int64_t* parent, int64_t* index,
+                      int32_t* attempts, double* logw)
+{
+    abcsmc_ctx* x = const_cast<abcsmc_ctx*>(cx);
+    if (!x) return fail(nullptr, ABCSMC_EINVAL, "ctx is NULL");
+    if (x->broken) return fail(&x->err, ABCSMC_ESTATE, "context unusable after a device error");
+    if (x->rounds == 0) return fail(&x->err, ABCSMC_ESTATE, "no completed stage");
+    const DevPop& p = x->pop[x->cur];
+    const size_t N = (size_t)x->N;
+    hipStream_t s = x->stream;
+    std::vector<int32_t> pi(parent ? N : 0);
+    std::vector<uint32_t> ii(index ? N : 0);
+    if (u) HIPCHK(x, hipMemcpyAsync(u, p.u, N * kNP * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (sigma) HIPCHK(x, hipMemcpyAsync(sigma, p.sigma, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (parent) HIPCHK(x, hipMemcpyAsync(pi.data(), p.parent, N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (index) HIPCHK(x, hipMemcpyAsync(ii.data(), p.index, N * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    if (attempts) HIPCHK(x, hipMemcpyAsync(attempts, p.att, N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (logw) HIPCHK(x, hipMemcpyAsync(logw, p.logw, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(x, hipStreamSynchronize(s));
+    for (size_t k = 0; k < pi.size(); ++k) parent[k] = pi[k];
+    for (size_t k = 0; k < ii.size(); ++k) index[k] = ii[k];
+    return ABCSMC_OK;
+}
+
+int abcsmc_resampling(const abcsmc_ctx* cx, uint64_t* q, uint64_t* cdf)
+{
+    abcsmc_ctx* x = const_cast<abcsmc_ctx*>(cx);
+    if (!x) return fail(nullptr, ABCSMC_EINVAL, "ctx is NULL");
+    if (x->broken) return fail(&x->err, ABCSMC_ESTATE, "context unusable after a device error");
+    if (x->rounds < 2) return fail(&x->err, ABCSMC_ESTATE, "no resampling before stage 1");
+    const size_t N = (size_t)x->N;
+    hipStream_t s = x->stream;
+    if (q) HIPCHK(x, hipMemcpyAsync(q, x->at<uint64_t>(x->L.q), N * 8, hipMemcpyDeviceToHost, s));
+    if (cdf) HIPCHK(x, hipMemcpyAsync(cdf, x->at<uint64_t>(x->L.cdf), N * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(x, hipStreamSynchronize(s));
+    return ABCSMC_OK;
+}
+
+int abcsmc_run(const abcsmc_config* cfg, const int64_t* obs, int32_t n_rounds, double* theta, double* dist,
+               double* weight, abcsmc_round_info* infos)
+{
+    if (n_rounds < 1) return fail(nullptr, ABCSMC_EINVAL, "n_rounds must be >= 1");
+    abcsmc_ctx* x = nullptr;
+    int rc = abcsmc_init(cfg, obs, &x);
+    if (rc) return rc;
+    for (int32_t i = 0; i < n_rounds && rc == ABCSMC_OK; ++i) rc = abcsmc_round(x, infos ? infos + i : nullptr);
+    if (rc == ABCSMC_OK) rc = abcsmc_weights(x, theta, dist, weight);
+    if (rc) g_last_error = x->err;
+    abcsmc_free(x);
+    return rc;
+}
+
+int abcsmc_simulate(const abcsmc_config* cfg, int64_t n, const double* theta, const int64_t* obs0, uint64_t seed,
+                    uint32_t round, uint32_t index0, int64_t* traj)
+{
+    std::string e;
+    int rc = validate(cfg, nullptr, &e);
+    if (rc) return rc;
+    if (n < 1 || !theta || !obs0 || !traj) return fail(nullptr, ABCSMC_EINVAL, "bad simulate arguments");
+    if (obs0[0] < 0 || obs0[1] < 0 || obs0[2] < 0 || obs0[0] + obs0[1] + obs0[2] > cfg->population)
+        return fail(nullptr, ABCSMC_EINVAL, "obs0 must be counts with A0+R0+D0 <= P");
+    if ((uint64_t)index0 + (uint64_t)n > ((uint64_t)1 << 32)) return fail(nullptr, ABCSMC_EINVAL, "index range exceeds 2^32");
+    TrajArgs ta{};
+    ta.m = make_model(*cfg, obs0);
+    ta.m.seed = seed;
+    ta.n = n;
+    ta.round = round;
+    ta.index0 = index0;
+    const size_t tb = (size_t)n * (size_t)(cfg->n_days + 1) * 6 * sizeof(int64_t);
+    double* dth = nullptr;
+    int64_t* dtr = nullptr;
+    hipStream_t s = (hipStream_t)cfg->stream;
+    auto cleanup = [&]() {
+        if (dth) (void)hipFree(dth);
+        if (dtr) (void)hipFree(dtr);
+    };
+    if (hipMalloc((void**)&dth, (size_t)n * kNP * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&dtr, tb) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return fail(nullptr, ABCSMC_ENOMEM, "hipMalloc failed in simulate");
+    }
+    ta.theta = dth;
+    ta.traj = dtr;
+    hipError_t err = hipMemcpyAsync(dth, theta, (size_t)n * kNP * sizeof(double), hipMemcpyHostToDevice, s);
+    if (err == hipSuccess) {
+        launch_simulate_traj(ta, s);
+        err = hipGetLastError();
+    }
+    if (err == hipSuccess) err = hipMemcpyAsync(traj, dtr, tb, hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    cleanup();
+    if (err != hipSuccess) return fail(nullptr, ABCSMC_EDEVICE, std::string("simulate: ") + hipGetErrorString(err));
+    return ABCSMC_OK;
+}
+
+int abcsmc_debug_eval(int32_t fn, int64_t n, const void* in, void* out, double param_a, int32_t param_b)
+{
+    if (n < 1 || !in || !out || fn < 0 || fn > 12) return fail(nullptr, ABCSMC_EINVAL, "bad debug_eval arguments");
+    if (fn == 11 && (param_b < 1 || param_b > 128)) return fail(nullptr, ABCSMC_EINVAL, "beta b out of range");
+    size_t in_b = 0, out_b = 0;
+    switch (fn) {
+    case 7: in_b = 16 * n; out_b = 8 * n; break;
+    case 8: in_b = 24 * n; out_b = 16 * n; break;
+    case 9: in_b = 8 * n; out_b = 16 * n; break;
+    case 10: case 12: in_b = 24 * n; out_b = 8 * n; break;
+    case 11: in_b = 8 * (size_t)n * param_b; out_b = 8 * n; break;
+    default: in_b = 8 * n; out_b = 8 * n; break;
+    }
+    void *din = nullptr, *dout = nullptr;
+    if (hipMalloc(&din, in_b) != hipSuccess || hipMalloc(&dout, out_b) != hipSuccess) {
+        (void)hipGetLastError();
+        if (din) (void)hipFree(din);
+        if (dout) (void)hipFree(dout);
+        return fail(nullptr, ABCSMC_ENOMEM, "hipMalloc failed in debug_eval");
+    }
+    hipError_t err = hipMemcpy(din, in, in_b, hipMemcpyHostToDevice);
+    if (err == hipSuccess) {
+        launch_debug_eval(fn, n, din, dout, param_a, param_b, nullptr);
+        err = hipGetLastError();
+    }
+    if (err == hipSuccess) err = hipMemcpy(out, dout, out_b, hipMemcpyDeviceToHost);
+    (void)hipFree(din);
+    (void)hipFree(dout);
+    if (err != hipSuccess) return fail(nullptr, ABCSMC_EDEVICE, std::string("debug_eval: ") + hipGetErrorString(err));
+    return ABCSMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+"""GPU parity of the device primitives against the oracle: IEEE division
+and square root, the series-based elementary functions, Philox, the normal
+pair, the binomial, Beta and floor-normal draws.  All bit-exact."""
+import numpy as np
+import pytest
+
+from paper_2106_15508_amd import abcsmc as A
+
+pytestmark = pytest.mark.gpu
+
+
+def _ev(fn, inp, n, out_dtype, out_shape, pa=0.0, pb=0):
+    out = np.zeros(out_shape, dtype=out_dtype)
+    return A.debug_eval(fn, inp, n, out, pa, pb)
+
+
+def _same(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    if a.dtype == np.float64:
+        return np.array_equal(a.view(np.uint64), b.view(np.uint64))
+    return np.array_equal(a, b)
+
+
+def _inputs():
+    rng = np.random.default_rng(2106)
+    return {
+        "exp": np.concatenate([rng.uniform(-708, 709.7, 20000), rng.uniform(-1, 1, 20000),
+                               [0.0, -0.0, -708.0, -707.99, 709.78, 1e-300, -1e-300]]),
+        "expm1": np.concatenate([rng.uniform(-0.35, 0.35, 20000), rng.uniform(-50, 5, 20000),
+                                 -(10 ** rng.uniform(-300, 2, 5000)), [0.0, -0.34657359027997264]]),
+        "log": np.concatenate([10 ** rng.uniform(-300, 300, 20000), rng.uniform(0.5, 2, 20000),
+                               [1.0, 2.0 ** -1074, np.nextafter(1, 0), np.nextafter(1, 2)]]),
+        "log1p": np.concatenate([rng.uniform(-0.999, 4, 20000), -(10 ** rng.uniform(-300, -0.01, 5000)),
+                                 10 ** rng.uniform(-300, 8, 5000), [0.0, -0.5, 0.41421356237309515]]),
+        "cos2pi": (rng.integers(0, 2**32, 30000) + 0.5) / 2**32,
+        "sin2pi": (rng.integers(0, 2**32, 30000) + 0.5) / 2**32,
+    }
+
+
+@pytest.mark.parametrize("name,fn", [("exp", 0), ("expm1", 1), ("log", 2), ("log1p", 3),
+                                     ("cos2pi", 4), ("sin2pi", 5)])
+def test_elementary_bitwise(oracle, name, fn):
+    x = _inputs()[name]
+    got = _ev(fn, x, x.size, np.float64, x.size)
+    want = oracle.fmap(name, x)
+    bad = np.flatnonzero(got.view(np.uint64) != want.view(np.uint64))
+    assert bad.size == 0, (name, x[bad[:5]], got[bad[:5]], want[bad[:5]])
+
+
+def test_sqrt_and_division_correctly_rounded():
+    """gfx950 FP64 sqrt and division are IEEE correctly rounded (numpy on
+    the host is the reference)."""
+    rng = np.random.default_rng(3)
+    x = np.concatenate([10 ** rng.uniform(-300, 300, 50000), rng.uniform(0, 4, 50000),
+                        (rng.integers(0, 2**52, 20000) + 0.5) * 2.0**-52 * 1e17])
+    got = _ev(6, x, x.size, np.float64, x.size)
+    assert _same(got, np.sqrt(x))
+    a = rng.uniform(-1e6, 1e6, 60000) * 10 ** rng.uniform(-100, 100, 60000)
+    b = rng.uniform(0.1, 10, 60000) * 10 ** rng.uniform(-100, 100, 60000)
+    pairs = np.stack([a, b], 1).ravel()
+    got = _ev(7, pairs, a.size, np.float64, a.size)
+    assert _same(got, a / b)
+
+
+def test_philox_bitwise(oracle):
+    rng = np.random.default_rng(4)
+    n = 4000
+    ck = rng.integers(0, 2**32, (n, 6), dtype=np.uint64).astype(np.uint32)
+    got = _ev(8, ck, n, np.uint32, (n, 4))
+    for i in range(0, n, 97):
+        assert np.array_equal(got[i], oracle.philox(ck[i, :4], ck[i, 4:]))
+
+
+def test_box_muller_bitwise(oracle):
+    w = np.random.default_rng(5).integers(0, 2**64, 30000, dtype=np.uint64)
+    got = _ev(9, w, w.size, np.float64, (w.size, 2))
+    assert _same(got, oracle.box_muller(w))
+
+
+def _draw_inputs(seed, cnt):
+    rng = np.random.default_rng(seed)
+    n = np.concatenate([rng.integers(0, 20, cnt // 4), rng.integers(0, 2000, cnt // 4),
+                        rng.integers(0, 10**6, cnt // 4), rng.integers(0, 3 * 10**8, cnt - 3 * (cnt // 4))])
+    p = np.concatenate([rng.uniform(0, 1, cnt // 2), 10 ** rng.uniform(-9, 0, cnt - cnt // 2)])
+    p[::17] = 0.0
+    p[::19] = 1.0
+    p[::23] = 0.5
+    w = rng.integers(0, 2**64, cnt, dtype=np.uint64)
+    rec = np.zeros((cnt, 3), dtype=np.uint64)
+    rec[:, 0] = n.astype(np.int64).view(np.uint64)
+    rec[:, 1] = p.view(np.uint64)
+    rec[:, 2] = w
+    return n.astype(np.int64), p, w, rec
+
+
+def test_binomial_bitwise(oracle):
+    n, p, w, rec = _draw_inputs(6, 40000)
+    got = _ev(10, rec, n.size, np.int64, n.size)
+    want = oracle.binomial(n, p, w)
+    bad = np.flatnonzero(got != want)
+    assert bad.size == 0, (n[bad[:5]], p[bad[:5]], got[bad[:5]], want[bad[:5]])
+
+
+def test_normal_floor_bitwise(oracle):
+    n, p, w, rec = _draw_inputs(7, 20000)
+    h = p * n  # use n p as the hazard
+    rec[:, 1] = h.view(np.uint64)
+    got = _ev(12, rec, n.size, np.int64, n.size)
+    L = oracle.lib()
+    want = np.array([L.ref_normal_floor(int(a), float(b), int(c)) for a, b, c in zip(n, h, w)])
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("a,b", [(1.0, 2), (0.5, 5), (0.1, 15), (2.0, 5), (0.003, 24), (1.0, 1)])
+def test_beta_bitwise(oracle, a, b):
+    cnt = 5000
+    w = np.random.default_rng(int(a * 1000) + b).integers(0, 2**64, (cnt, b), dtype=np.uint64)
+    got = _ev(11, w, cnt, np.float64, cnt, a, b)
+    assert _same(got, oracle.beta_int(a, b, w))

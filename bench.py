@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Throughput of the ABC-SMC BDSS hot path on one MI355X.
+
+One step is one complete ABC-SMC run of the headline workload (population
+1e7, 120 days, N = 131072 particles, 10 stages: the prior stage plus nine
+stages with eq. 16 step sizes): resampling, Beta-step perturbation,
+simulation, distance, acceptance with ordered compaction, importance
+weights and the next tolerance, all in the HIP library.  The observations
+and the workspace are resident in HBM before the timed region; each step
+restarts the context at stage 0 (abcsmc_reset), so every step does the same
+work.
+
+Prints one JSON line: accepted particles/s (value), simulations/s, the
+roofline of the dominant kernel (device time from HIP events recorded on the
+library's stream around each launch), and the CPU oracle timed on a bounded
+sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--workload c2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+# FP64 flops (fma = 2) of one importance-weight term: 8 differences, 8 fma
+# for the squared distance, 1 scaling, exp (33: reduction 6, degree-13
+# polynomial 26, scale 1), 1 fma accumulation.
+FLOPS_PER_PAIR = 8 + 16 + 1 + 33 + 2
+# FP64 flops of one simulated proposal-day with all five transitions in the
+# normal branch of the binomial draw: state sums 2, g (log 34, exp 33, 4) 71,
+# rate 2, p_SI (expm1) 29, five draws 5 x 93, chain sources 2, update 10,
+# distance 9.
+FLOPS_PER_DAY = 2 + 71 + 2 + 29 + 5 * 93 + 2 + 10 + 9
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--early-exit", type=int, default=1, help="stop simulating a proposal once its "
+                    "partial distance exceeds eps (acceptances unchanged)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--verbose", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, infos, budget_s: float):
+    """Oracle (single thread, as it stands) on a bounded sample of the same
+    workload: (a) simulate proposals of stage 0 at full size until half the
+    budget is spent, (b) importance-weight rows against a synthetic previous
+    population of the stage's survivor count until the other half is spent;
+    the per-unit costs are scaled by the stage's own proposal and pair counts
+    (identical in the oracle, whose runs match the GPU bit for bit)."""
+    import numpy as np
+    from oracle import ref
+
+    obs = ref.observations(w)
+    t0 = time.perf_counter()
+    n_sim = 0
+    while time.perf_counter() - t0 < budget_s / 2:
+        u = ref.prior_draw(w, n_sim)
+        ref.sim_distance(w, obs, u, 0, n_sim)
+        n_sim += 1
+    t_sim = (time.perf_counter() - t0) / n_sim
+    rng = np.random.default_rng(0)
+    M = int(np.median([i["survivors"] for i in infos[1:]])) if len(infos) > 1 else w.n_particles // 2
+    u_prev = rng.uniform(size=(M, 8))
+    q = rng.integers(1, 2**40, M).astype(np.uint64)
+    t0 = time.perf_counter()
+    n_rows = 0
+    while time.perf_counter() - t0 < budget_s / 2:
+        ref.log_weight(rng.uniform(size=8), 0.05, u_prev, q)
+        n_rows += 1
+    t_pair = (time.perf_counter() - t0) / (n_rows * M)
+    sims = sum(i["simulated"] for i in infos)
+    pairs = sum(i["weight_pairs"] for i in infos)
+    t_run = sims * t_sim + pairs * t_pair
+    acc = w.n_particles * len(infos)
+    return {
+        "value": acc / t_run, "unit": "accepted particles/s", "cores": 1, "kind": "oracle",
+        "sample": (f"{n_sim} stage-0 proposals simulated ({w.n_days} days, P={w.population:.0e}) and "
+                   f"{n_rows} weight rows x {M} columns on 1 core; per-proposal and per-pair costs scaled "
+                   f"by the run's {sims} simulated proposals and {pairs} weight terms"),
+        "sec_per_sim": t_sim, "sec_per_pair": t_pair, "extrapolated_run_s": t_run,
+    }
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the ABC-SMC path here runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2106_15508_amd import abcsmc as A
+    from paper_2106_15508_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    w = W.WORKLOADS[args.workload]
+    R = w.n_rounds
+    obs = A.observations(w)                       # synthetic series from THETA_TRUE (on the GPU)
+    ws_tensor, ws = A.torch_workspace(w)          # workspace: device memory owned by torch
+    stream = torch.cuda.current_stream()
+    flags = A.F_EARLY_EXIT if args.early_exit else 0
+    ctx = A.Context(w, obs, stream=stream.cuda_stream, workspace=ws, flags=flags)
+
+    for _ in range(args.warmup):
+        ctx.reset()
+        ctx.run(R)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = []
+    for _ in range(args.steps):
+        ctx.reset()
+        steps.append(ctx.run(R))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec = (t1 - t0) / args.steps
+    last = steps[-1]
+    N = w.n_particles
+    accepted = N * R
+    simulated = sum(i["simulated"] for i in last)
+    proposals = sum(i["proposals"] for i in last)
+    sim_days = sum(i["sim_days"] for i in last)
+
+    # dominant kernel over the timed steps
+    ms_prop = sum(i["ms_k_propose"] for s in steps for i in s)
+    n_prop = sum(i["n_k_propose"] for s in steps for i in s)
+    ms_w = sum(i["ms_k_weights"] for s in steps for i in s)
+    n_w = sum(1 for s in steps for i in s if i["round"] > 0)
+    if ms_w >= ms_prop:
+        flops = sum(i["weight_pairs"] for s in steps for i in s) * FLOPS_PER_PAIR
+        kernel, avg_ms, launches = "weights_kernel", ms_w / n_w, n_w
+    else:
+        flops = sum(i["sim_days"] for s in steps for i in s) * FLOPS_PER_DAY
+        kernel, avg_ms, launches = "propose_kernel", ms_prop / n_prop, n_prop
+    achieved = flops / launches / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "kernel": kernel, "avg_launch_ms": round(avg_ms, 4), "launches": launches,
+                "flops_per_launch": flops / launches}
+
+    out = {
+        "metric": "accepted particles/s", "value": accepted / sec, "unit": "accepted particles/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: P={w.population}, T={w.n_days}, N={N}, stages={R}, "
+                               "eq.16 Beta step sizes, chain-binomial simulator, synthetic observations "
+                               "of theta_true",
+                   "early_exit": bool(args.early_exit)},
+        "simulations_per_s": simulated / sec,
+        "useful_simulations_per_s": proposals / sec,
+        "particle_days_per_s": sim_days / sec,
+        "eps_final": last[-1]["eps_next"],
+        "phase_ms": {k: round(sum(i[k] for i in last), 3)
+                     for k in ("ms_resample", "ms_simulate", "ms_weights", "ms_select", "ms_total")},
+        "kernel_ms": {"propose": round(ms_prop / args.steps, 3), "weights": round(ms_w / args.steps, 3)},
+        "roofline": roofline,
+    }
+    if args.verbose:
+        for i in last:
+            print(json.dumps(i), file=sys.stderr)
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(w, last, args.cpu_seconds)
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline"]["gpu_over_cpu"] = out["value"] / cb["value"]
+    ctx.close()
+    del ws_tensor
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -105,11 +105,16 @@ typedef struct {
     double ess;                   /* effective sample size of the importance weights */
     int64_t proposals;            /* proposals up to and including the N-th acceptance */
     int64_t simulated;            /* proposals simulated (whole batches, incl. past the N-th acceptance) */
-    int64_t invalid;              /* void proposals (no in-cube perturbation) among `proposals` */
+    int64_t invalid;              /* void proposals (no in-cube perturbation) among `simulated` */
     int64_t attempts;             /* perturbation attempts over `simulated` */
     int64_t survivors;            /* previous-stage particles with resampling weight > 0 (eqs. 9-10) */
     int64_t batches;              /* batches launched */
     double ms_resample, ms_simulate, ms_weights, ms_select, ms_total; /* device time per phase */
+    double ms_k_propose;          /* summed device time of the proposal kernel launches */
+    double ms_k_weights;          /* device time of the importance-weight kernel */
+    int64_t n_k_propose;          /* proposal kernel launches (= batches) */
+    int64_t sim_days;             /* proposal-days simulated (early exit stops counting) */
+    int64_t weight_pairs;         /* N x survivors terms of the importance-weight sums */
 } abcsmc_round_info;
 
 typedef struct abcsmc_ctx abcsmc_ctx;
@@ -143,6 +148,11 @@ int abcsmc_population(const abcsmc_ctx* ctx, double* u, double* sigma, int64_t* 
  * q N (quantised weights of the previous stage), cdf N (inclusive prefix sum).
  * ABCSMC_ESTATE before stage 1. */
 int abcsmc_resampling(const abcsmc_ctx* ctx, uint64_t* q, uint64_t* cdf);
+
+/* Restart the context at stage 0 with the same configuration and seed
+ * (the workspace and observations stay resident).  The next abcsmc_round
+ * repeats the run bit for bit. */
+int abcsmc_reset(abcsmc_ctx* ctx);
 
 /* Stages completed so far. */
 int abcsmc_rounds_done(const abcsmc_ctx* ctx);

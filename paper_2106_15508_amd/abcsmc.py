@@ -28,7 +28,7 @@ F_STEP_IS_VARIANCE = 2
 #: every function the header declares
 EXPORTS = (
     "abcsmc_workspace_size", "abcsmc_init", "abcsmc_round", "abcsmc_weights", "abcsmc_population",
-    "abcsmc_resampling", "abcsmc_rounds_done", "abcsmc_run", "abcsmc_simulate", "abcsmc_debug_eval",
+    "abcsmc_resampling", "abcsmc_reset", "abcsmc_rounds_done", "abcsmc_run", "abcsmc_simulate", "abcsmc_debug_eval",
     "abcsmc_free", "abcsmc_strerror", "abcsmc_last_error", "abcsmc_abi_version",
 )
 
@@ -59,7 +59,8 @@ class RoundInfo(C.Structure):
         ("simulated", C.c_int64), ("invalid", C.c_int64), ("attempts", C.c_int64),
         ("survivors", C.c_int64), ("batches", C.c_int64), ("ms_resample", C.c_double),
         ("ms_simulate", C.c_double), ("ms_weights", C.c_double), ("ms_select", C.c_double),
-        ("ms_total", C.c_double),
+        ("ms_total", C.c_double), ("ms_k_propose", C.c_double), ("ms_k_weights", C.c_double),
+        ("n_k_propose", C.c_int64), ("sim_days", C.c_int64), ("weight_pairs", C.c_int64),
     ]
 
     def as_dict(self):
@@ -86,6 +87,7 @@ def load(path: Optional[str] = None):
         "abcsmc_weights": (C.c_int, [vp, vp, vp, vp]),
         "abcsmc_population": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "abcsmc_resampling": (C.c_int, [vp, vp, vp]),
+        "abcsmc_reset": (C.c_int, [vp]),
         "abcsmc_rounds_done": (C.c_int, [vp]),
         "abcsmc_run": (C.c_int, [vp, vp, i32, vp, vp, vp, vp]),
         "abcsmc_simulate": (C.c_int, [vp, i64, vp, vp, u64, u32, u32, vp]),
@@ -200,6 +202,11 @@ class Context:
 
     def run(self, n_rounds: int) -> List[dict]:
         return [self.round() for _ in range(n_rounds)]
+
+    def reset(self):
+        """Restart at stage 0 (same config and seed; workspace stays resident)."""
+        _check(self.L.abcsmc_reset(self._h), self._h)
+        self.infos = []
 
     def rounds_done(self) -> int:
         return self.L.abcsmc_rounds_done(self._h)

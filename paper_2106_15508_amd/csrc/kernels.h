@@ -31,7 +31,7 @@ struct StageCounters {
     unsigned long long base_rank;  // acceptances before the current batch
     unsigned long long survivors;  // previous particles with q > 0
     unsigned long long fallback;   // 1 if the prior set used d <= eps (no d < eps)
-    unsigned long long pad;
+    unsigned long long days;       // proposal-days simulated over the batches run so far
 };
 
 // Population of one stage, array-of-structures for the per-particle gathers.

@@ -174,7 +174,7 @@ struct abcsmc_ctx {
     bool own_ws = false;
     bool broken = false;
     std::string err;
-    hipEvent_t ev[6] = {};
+    hipEvent_t ev[9] = {};
     DevPop pop[2]{};
     int cur = 0;                 // pop[cur] holds the last completed stage
     int32_t rounds = 0;          // stages completed
@@ -326,6 +326,18 @@ int abcsmc_init(const abcsmc_config* cfg, const int64_t* obs, abcsmc_ctx** out)
 
 int abcsmc_rounds_done(const abcsmc_ctx* ctx) { return ctx ? ctx->rounds : ABCSMC_EINVAL; }
 
+int abcsmc_reset(abcsmc_ctx* x)
+{
+    if (!x) return fail(nullptr, ABCSMC_EINVAL, "ctx is NULL");
+    if (x->broken) return fail(&x->err, ABCSMC_ESTATE, "context unusable after a device error");
+    x->rounds = 0;
+    x->cur = 0;
+    x->eps_next = INFINITY;
+    x->eps1 = INFINITY;
+    x->last_rate = 0.5;
+    return ABCSMC_OK;
+}
+
 int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
 {
     if (!x) return fail(nullptr, ABCSMC_EINVAL, "ctx is NULL");
@@ -402,6 +414,7 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
 
     const int64_t cap = batch_cap(c);
     int64_t base = 0, batches = 0;
+    double ms_k_propose = 0.0;
     StageCounters hc{};
     for (;;) {
         int64_t B;
@@ -420,14 +433,17 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
         if (B <= 0) return fail(&x->err, ABCSMC_EBUDGET, "stage exhausted its proposal budget");
         pa.base = (uint32_t)base;
         pa.count = (uint32_t)B;
+        HIPCHK(x, hipEventRecord(x->ev[5], s));
         launch_propose(pa, r == 0, s);
         HIPCHK(x, hipGetLastError());
+        HIPCHK(x, hipEventRecord(x->ev[6], s));
         ca.base = pa.base;
         ca.count = pa.count;
         launch_compact(ca, s);
         HIPCHK(x, hipGetLastError());
         HIPCHK(x, hipMemcpyAsync(&hc, ctr, sizeof hc, hipMemcpyDeviceToHost, s));
         HIPCHK(x, hipStreamSynchronize(s));
+        ms_k_propose += elapsed(x->ev[5], x->ev[6]);
         base += B;
         ++batches;
         if (hc.accepted >= (unsigned long long)N) break;
@@ -439,8 +455,10 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
         launch_uniform_weights(dst.W, dst.logw, N, s);
     } else {
         WeightArgs wa{dst.u, dst.sigma, x->at<double>(x->L.cols), N, &ctr->survivors, dst.logw};
+        HIPCHK(x, hipEventRecord(x->ev[7], s));
         launch_weights(wa, s);
         HIPCHK(x, hipGetLastError());
+        HIPCHK(x, hipEventRecord(x->ev[8], s));
         NormArgs na{dst.logw, dst.W, N, scal + 1};
         launch_normalise(na, s);
     }
@@ -479,6 +497,11 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
         I.ms_weights = elapsed(x->ev[2], x->ev[3]);
         I.ms_select = elapsed(x->ev[3], x->ev[4]);
         I.ms_total = elapsed(x->ev[0], x->ev[4]);
+        I.ms_k_propose = ms_k_propose;
+        I.ms_k_weights = r == 0 ? 0.0 : elapsed(x->ev[7], x->ev[8]);
+        I.n_k_propose = batches;
+        I.sim_days = (int64_t)hc.days;
+        I.weight_pairs = r == 0 ? 0 : (int64_t)N * (int64_t)hc.survivors;
     }
     return ABCSMC_OK;
 }

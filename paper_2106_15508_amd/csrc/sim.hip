@@ -23,7 +23,8 @@ namespace {
 template <int kSampler, bool kTraj>
 __device__ __forceinline__ double simulate_distance(const Model& m, const double* th,
                                                     const double* __restrict__ obs, uint32_t round,
-                                                    uint32_t index, double exit_thr, int64_t* traj)
+                                                    uint32_t index, double exit_thr, int64_t* traj,
+                                                    int32_t& days)
 {
     const double alpha0 = th[0], alpha_c = th[1], n_exp = th[2], beta = th[3];
     const double gamma = th[4], delta = th[5], eta = th[6], kappa = th[7];
@@ -90,9 +91,13 @@ __device__ __forceinline__ double simulate_distance(const Model& m, const double
             acc = acc + dA * dA;
             acc = acc + dR * dR;
             acc = acc + dD * dD;
-            if (acc > exit_thr) return __builtin_inf();
+            if (acc > exit_thr) {
+                days = t + 1;
+                return __builtin_inf();
+            }
         }
     }
+    days = m.T;
     return __builtin_sqrt(acc);
 }
 
@@ -197,11 +202,12 @@ __global__ __launch_bounds__(kBlock) void propose_kernel(ProposeArgs a)
     }
     double d = __builtin_inf();
     bool acc = false;
+    int32_t days = 0;
     if (valid) {
         double th[kNP];
 #pragma unroll
         for (int q = 0; q < kNP; ++q) th[q] = a.m.lo[q] + u[q] * a.m.width[q];
-        d = simulate_distance<kSampler, false>(a.m, th, a.obs, a.round, j, a.exit_thr, nullptr);
+        d = simulate_distance<kSampler, false>(a.m, th, a.obs, a.round, j, a.exit_thr, nullptr, days);
         acc = d <= a.eps;
     }
     if (active) {
@@ -216,10 +222,12 @@ __global__ __launch_bounds__(kBlock) void propose_kernel(ProposeArgs a)
     const unsigned long long mask = __ballot(acc);
     const unsigned long long inv = wave_sum_u64((active && !valid) ? 1ull : 0ull);
     const unsigned long long natt = wave_sum_u64(active ? (unsigned long long)(att < 0 ? -att : att) : 0ull);
+    const unsigned long long ndays = wave_sum_u64((unsigned long long)days);
     if ((threadIdx.x & (kWave - 1)) == 0) {
         a.wave_mask[p / kWave] = mask;
         if (inv) atomicAdd(&a.ctr->invalid, inv);
         if (natt) atomicAdd(&a.ctr->attempts, natt);
+        if (ndays) atomicAdd(&a.ctr->days, ndays);
     }
 }
 
@@ -291,8 +299,9 @@ __global__ __launch_bounds__(kBlock) void simulate_traj_kernel(TrajArgs a)
     for (int q = 0; q < kNP; ++q) th[q] = a.theta[k * kNP + q];
     int64_t* traj = a.traj + (size_t)k * (size_t)(a.m.T + 1) * 6;
     // a bare trajectory: no observations, no distance
+    int32_t days = 0;
     simulate_distance<kSampler, true>(a.m, th, nullptr, a.round, a.index0 + (uint32_t)k,
-                                      __builtin_inf(), traj);
+                                      __builtin_inf(), traj, days);
 }
 
 __global__ __launch_bounds__(kBlock) void debug_eval_kernel(int32_t fn, int64_t n, const void* in,

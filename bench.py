@@ -34,9 +34,21 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 # FP64 flops (fma = 2) of one importance-weight term: 8 differences, 8 fma
-# for the squared distance, 1 scaling, exp (33: reduction 6, degree-13
-# polynomial 26, scale 1), 1 fma accumulation.
-FLOPS_PER_PAIR = 8 + 16 + 1 + 33 + 2
+# for the squared distance, 1 scaling, table exp (18: scale and round 2,
+# two-part reduction 4, degree-5 polynomial 10, table product 1, 2^k 1),
+# weight product 1, accumulation 1.
+FLOPS_PER_PAIR = 8 + 16 + 1 + 18 + 1 + 1
+
+# HBM bytes per launch of the dominant kernel measured with rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE on this workload, scaled by the counters' reading
+# for a 256 MiB device copy (FETCH 0.5x, WRITE 1.0x of the bytes moved).  Keyed
+# by the SHA-256 of the kernel sources: a changed kernel reports null.
+TRAFFIC_SOURCES = ("paper_2106_15508_amd/csrc/smc.hip", "paper_2106_15508_amd/csrc/dmath.h",
+                   "paper_2106_15508_amd/csrc/kernels.h")
+TRAFFIC_MEASURED = {
+    # weights_kernel, c2: FETCH_SIZE 23073 KiB x 2 + WRITE_SIZE 4096 KiB x 1 per launch
+    ("227281976887633a", "c2", "weights_kernel"): 23073 * 1024 * 2 + 4096 * 1024,
+}
 # FP64 flops of one simulated proposal-day with all five transitions in the
 # normal branch of the binomial draw: state sums 2, g (log 34, exp 33, 4) 71,
 # rate 2, p_SI (expm1) 29, five draws 5 x 93, chain sources 2, update 10,
@@ -55,7 +67,19 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="first run one device-to-device copy of BYTES (the plain copy kernel that "
+                         "scales the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def kernel_sources_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(w, infos, budget_s: float):
@@ -112,6 +136,13 @@ def main():
     from paper_2106_15508_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = W.WORKLOADS[args.workload]
     R = w.n_rounds
     obs = A.observations(w)                       # synthetic series from THETA_TRUE (on the GPU)
@@ -151,10 +182,12 @@ def main():
         flops = sum(i["sim_days"] for s in steps for i in s) * FLOPS_PER_DAY
         kernel, avg_ms, launches = "propose_kernel", ms_prop / n_prop, n_prop
     achieved = flops / launches / (avg_ms * 1e-3) / 1e12
+    sha = kernel_sources_sha()
+    traffic = TRAFFIC_MEASURED.get((sha, args.workload, kernel))
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
                 "kernel": kernel, "avg_launch_ms": round(avg_ms, 4), "launches": launches,
-                "flops_per_launch": flops / launches}
+                "flops_per_launch": flops / launches, "kernel_sources_sha": sha}
 
     out = {
         "metric": "accepted particles/s", "value": accepted / sec, "unit": "accepted particles/s",

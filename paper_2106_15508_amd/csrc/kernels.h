@@ -87,6 +87,18 @@ struct CompactArgs {
     StageCounters* ctr;
 };
 
+// Per-block partial results of the multi-block reductions and scans.
+constexpr int kRedMax = 4096;  // max blocks of a reduction (N <= 2^22 at 1024 per block)
+struct Scratch {
+    unsigned long long* u0;  // kRedMax
+    unsigned long long* u1;  // kRedMax
+    unsigned long long* u2;  // kRedMax
+    double* d0;              // kRedMax
+    double* d1;              // kRedMax
+    unsigned int* hist;      // 2 x 2048 radix-select bins
+    unsigned long long* sel; // radix-select state: prefix[2], mask[2], rank[2], r0, r1
+};
+
 struct ResampleArgs {
     const double* d_prev;   // N
     const double* u_prev;   // N x 8
@@ -95,6 +107,7 @@ struct ResampleArgs {
     uint64_t* q;            // N
     uint64_t* cdf;          // N
     double* cols;           // M x 9: u_k[8], q_k  (q_k > 0 only, index order)
+    Scratch sc;
     StageCounters* ctr;
 };
 
@@ -103,14 +116,23 @@ struct WeightArgs {
     const double* sigma;    // N
     const double* cols;     // M x 9
     int32_t N;
+    int32_t chunks;         // column chunks (second grid dimension)
     const unsigned long long* M;  // device scalar: survivors
+    double* partial;        // chunks x N row sums per column chunk
     double* logw;           // N
+    // exp by table: 64/ln2, ln2/64 (hi, lo), Taylor 1/2!, 1/3!, 1/4!, 1/5! (kernel
+    // arguments so they sit in scalar registers)
+    double ex[7];
 };
+
+// Fill WeightArgs::ex.
+void weight_exp_constants(double ex[7]);
 
 struct NormArgs {
     const double* logw;
     double* W;
     int32_t N;
+    Scratch sc;
     double* ess;            // device scalar
 };
 
@@ -118,8 +140,13 @@ struct SelectArgs {
     const double* x;        // N non-negative (or +inf) values
     int32_t N;
     double alpha;
+    Scratch sc;
     double* out;            // device scalar: type-7 quantile
 };
+
+// Column chunks of the weight kernel for N rows: enough workgroups to give
+// every SIMD about eight waves, with the partial sums bounded by 2^23 doubles.
+int weight_chunks(int64_t N);
 
 struct TrajArgs {
     Model m;

@@ -35,7 +35,7 @@ struct DevPop {
 // Byte layout of the device workspace (every region 256-byte aligned).
 struct Layout {
     size_t obs, pop[2][8], q, cdf, cols, st_u, st_d, st_sigma, st_parent, st_att, wave_mask, wave_off,
-        ctr, scal, theta, total;
+        ctr, scal, theta, red[5], hist, sel, wpart, total;
 };
 
 constexpr size_t kAlign = 256;
@@ -90,6 +90,10 @@ Layout make_layout(const abcsmc_config& c)
     L.ctr = take(sizeof(StageCounters));
     L.scal = take(8 * sizeof(double));
     L.theta = take(N * kNP * sizeof(double));
+    for (int r = 0; r < 5; ++r) L.red[r] = take(kRedMax * 8);
+    L.hist = take(2 * 2048 * sizeof(unsigned int));
+    L.sel = take(8 * sizeof(unsigned long long));
+    L.wpart = take((size_t)weight_chunks((int64_t)N) * N * sizeof(double));
     L.total = o;
     return L;
 }
@@ -184,6 +188,12 @@ struct abcsmc_ctx {
     int64_t N = 0;
     template <typename T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+    Scratch scratch() const
+    {
+        return Scratch{at<unsigned long long>(L.red[0]), at<unsigned long long>(L.red[1]),
+                       at<unsigned long long>(L.red[2]), at<double>(L.red[3]), at<double>(L.red[4]),
+                       at<unsigned int>(L.hist), at<unsigned long long>(L.sel)};
+    }
 };
 
 namespace {
@@ -374,7 +384,7 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
     HIPCHK(x, hipEventRecord(x->ev[0], s));
     if (r > 0) {
         ResampleArgs ra{prev.d, prev.u, N, eps, x->at<uint64_t>(x->L.q), x->at<uint64_t>(x->L.cdf),
-                        x->at<double>(x->L.cols), ctr};
+                        x->at<double>(x->L.cols), x->scratch(), ctr};
         launch_resample(ra, s);
         HIPCHK(x, hipGetLastError());
     }
@@ -454,17 +464,19 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
     if (r == 0) {
         launch_uniform_weights(dst.W, dst.logw, N, s);
     } else {
-        WeightArgs wa{dst.u, dst.sigma, x->at<double>(x->L.cols), N, &ctr->survivors, dst.logw};
+        WeightArgs wa{dst.u, dst.sigma, x->at<double>(x->L.cols), N, weight_chunks(N), &ctr->survivors,
+                      x->at<double>(x->L.wpart), dst.logw, {}};
+        weight_exp_constants(wa.ex);
         HIPCHK(x, hipEventRecord(x->ev[7], s));
         launch_weights(wa, s);
         HIPCHK(x, hipGetLastError());
         HIPCHK(x, hipEventRecord(x->ev[8], s));
-        NormArgs na{dst.logw, dst.W, N, scal + 1};
+        NormArgs na{dst.logw, dst.W, N, x->scratch(), scal + 1};
         launch_normalise(na, s);
     }
     HIPCHK(x, hipGetLastError());
     HIPCHK(x, hipEventRecord(x->ev[3], s));
-    SelectArgs sa{dst.d, N, c.surv_ratio, scal + 0};
+    SelectArgs sa{dst.d, N, c.surv_ratio, x->scratch(), scal + 0};
     launch_select(sa, s);
     HIPCHK(x, hipGetLastError());
     HIPCHK(x, hipEventRecord(x->ev[4], s));

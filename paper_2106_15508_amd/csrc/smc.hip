@@ -3,6 +3,8 @@
 //   weights    N x M importance-weight row sums, LDS-tiled, FP64
 //   normalise  W = softmax(log-weights), effective sample size
 //   select     exact type-7 percentile of eq. 8 by radix select
+// All reductions combine per-block partials in a fixed order, so every result
+// is bitwise reproducible run to run.
 #include "dmath.h"
 #include "kernels.h"
 
@@ -10,29 +12,43 @@ namespace abcsmc {
 
 namespace {
 
-constexpr int kOne = 1024;  // threads of the single-workgroup kernels
+constexpr int kChunk = 1024;            // elements per block of the resample kernels
+constexpr int kPer = kChunk / kBlock;   // elements per thread (contiguous)
 
-template <typename T>
-__device__ __forceinline__ T block_reduce_sum(T v, T* sh)
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v, unsigned long long* sh)
 {
     const int t = threadIdx.x;
     sh[t] = v;
     __syncthreads();
-    for (int off = kOne / 2; off > 0; off >>= 1) {
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
         if (t < off) sh[t] += sh[t + off];
         __syncthreads();
     }
-    const T r = sh[0];
+    const unsigned long long r = sh[0];
     __syncthreads();
     return r;
 }
 
-__device__ __forceinline__ double block_reduce_max(double v, double* sh)
+__device__ __forceinline__ double block_sum_f64(double v, double* sh)
 {
     const int t = threadIdx.x;
     sh[t] = v;
     __syncthreads();
-    for (int off = kOne / 2; off > 0; off >>= 1) {
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (t < off) sh[t] += sh[t + off];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double block_max_f64(double v, double* sh)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
         if (t < off) sh[t] = sh[t] > sh[t + off] ? sh[t] : sh[t + off];
         __syncthreads();
     }
@@ -41,22 +57,23 @@ __device__ __forceinline__ double block_reduce_max(double v, double* sh)
     return r;
 }
 
-// Inclusive scan of one value per thread (Hillis-Steele in LDS).
-template <typename T>
-__device__ __forceinline__ T block_scan_incl(T v, T* sh)
+// Exclusive scan of one value per thread (Hillis-Steele in LDS); *total gets the sum.
+__device__ __forceinline__ unsigned long long block_excl_scan_u64(unsigned long long v, unsigned long long* sh,
+                                                                  unsigned long long* total)
 {
     const int t = threadIdx.x;
     sh[t] = v;
     __syncthreads();
-    for (int off = 1; off < kOne; off <<= 1) {
-        const T x = t >= off ? sh[t - off] : (T)0;
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const unsigned long long x = t >= off ? sh[t - off] : 0ull;
         __syncthreads();
         sh[t] += x;
         __syncthreads();
     }
-    const T r = sh[t];
+    const unsigned long long incl = sh[t];
+    *total = sh[kBlock - 1];
     __syncthreads();
-    return r;
+    return incl - v;
 }
 
 // ---------------------------------------------------------------------------
@@ -66,68 +83,136 @@ __device__ __forceinline__ T block_scan_incl(T v, T* sh)
 // w_max = 0); cdf = inclusive prefix sum of q, exact in uint64 (eq. 11 draws
 // r uniform in [0, cdf[N-1]) and takes the first k with cdf[k] > r).  Also
 // packs (u_k, q_k) of every q_k > 0 in index order for the weight kernel.
-// One workgroup, contiguous chunks per thread.
+// Three passes over blocks of 1024 particles: statistics, per-block sums,
+// write-out with the block's exclusive offset.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kOne) void resample_kernel(ResampleArgs a)
+__global__ __launch_bounds__(kBlock) void resample_stats_kernel(ResampleArgs a)
 {
-    __shared__ unsigned long long shu[kOne];
-    __shared__ double shd[kOne];
-    const int t = threadIdx.x;
-    const int N = a.N;
-    const double eps = a.eps;
-    unsigned long long ns = 0, nle = 0;
+    __shared__ unsigned long long shu[kBlock];
+    __shared__ double shd[kBlock];
+    const int k0 = blockIdx.x * kChunk;
+    unsigned long long ns = 0;
     double wmx = 0.0;
-    for (int k = t; k < N; k += kOne) {
-        const double d = a.d_prev[k];
-        if (d < eps) {
-            ++ns;
-            const double w = eps - d;
-            wmx = w > wmx ? w : wmx;
+    for (int i = 0; i < kPer; ++i) {
+        const int k = k0 + i * kBlock + threadIdx.x;
+        if (k < a.N) {
+            const double d = a.d_prev[k];
+            if (d < a.eps) {
+                ++ns;
+                const double w = a.eps - d;
+                wmx = w > wmx ? w : wmx;
+            }
         }
-        nle += d <= eps;
     }
-    ns = block_reduce_sum(ns, shu);
-    nle = block_reduce_sum(nle, shu);
-    wmx = block_reduce_max(wmx, shd);
-    const bool strict = ns > 0;
-    const double wmax = strict ? wmx : 0.0;
+    ns = block_sum_u64(ns, shu);
+    wmx = block_max_f64(wmx, shd);
+    if (threadIdx.x == 0) {
+        a.sc.u0[blockIdx.x] = ns;
+        a.sc.d0[blockIdx.x] = wmx;
+    }
+}
 
-    const int chunk = (N + kOne - 1) / kOne;
-    const int k0 = min(N, t * chunk), k1 = min(N, k0 + chunk);
-    unsigned long long sq = 0, sc = 0;
-    for (int k = k0; k < k1; ++k) {
-        const double d = a.d_prev[k];
-        const bool in = strict ? (d < eps) : (d <= eps);
-        unsigned long long q = 0;
-        if (in) q = wmax > 0.0 ? (unsigned long long)__builtin_floor(((eps - d) / wmax) * 0x1p40) : 1ull;
-        sq += q;
-        sc += q > 0;
+// Global prior-set mode from the per-block statistics (same order in every block).
+__device__ __forceinline__ void resample_mode(const ResampleArgs& a, bool& strict, double& wmax,
+                                              unsigned long long* shu, double* shd)
+{
+    const int G = gridDim.x;
+    unsigned long long ns = 0;
+    double wmx = 0.0;
+    for (int b = threadIdx.x; b < G; b += kBlock) {
+        ns += a.sc.u0[b];
+        wmx = a.sc.d0[b] > wmx ? a.sc.d0[b] : wmx;
     }
-    const unsigned long long qi = block_scan_incl(sq, shu);
-    const unsigned long long ci = block_scan_incl(sc, shu);
-    unsigned long long run = qi - sq, col = ci - sc;
-    for (int k = k0; k < k1; ++k) {
-        const double d = a.d_prev[k];
-        const bool in = strict ? (d < eps) : (d <= eps);
-        unsigned long long q = 0;
-        if (in) q = wmax > 0.0 ? (unsigned long long)__builtin_floor(((eps - d) / wmax) * 0x1p40) : 1ull;
-        run += q;
-        a.q[k] = q;
+    ns = block_sum_u64(ns, shu);
+    wmx = block_max_f64(wmx, shd);
+    strict = ns > 0;
+    wmax = strict ? wmx : 0.0;
+}
+
+__device__ __forceinline__ unsigned long long quantise(double d, double eps, bool strict, double wmax)
+{
+    const bool in = strict ? (d < eps) : (d <= eps);
+    if (!in) return 0ull;
+    return wmax > 0.0 ? (unsigned long long)__builtin_floor(((eps - d) / wmax) * 0x1p40) : 1ull;
+}
+
+__global__ __launch_bounds__(kBlock) void resample_count_kernel(ResampleArgs a)
+{
+    __shared__ unsigned long long shu[kBlock];
+    __shared__ double shd[kBlock];
+    bool strict;
+    double wmax;
+    resample_mode(a, strict, wmax, shu, shd);
+    const int k0 = blockIdx.x * kChunk + threadIdx.x * kPer;
+    unsigned long long sq = 0, sc = 0;
+    for (int i = 0; i < kPer; ++i) {
+        const int k = k0 + i;
+        if (k < a.N) {
+            const unsigned long long q = quantise(a.d_prev[k], a.eps, strict, wmax);
+            sq += q;
+            sc += q > 0;
+        }
+    }
+    sq = block_sum_u64(sq, shu);
+    sc = block_sum_u64(sc, shu);
+    if (threadIdx.x == 0) {
+        a.sc.u1[blockIdx.x] = sq;
+        a.sc.u2[blockIdx.x] = sc;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void resample_write_kernel(ResampleArgs a)
+{
+    __shared__ unsigned long long shu[kBlock];
+    __shared__ double shd[kBlock];
+    bool strict;
+    double wmax;
+    resample_mode(a, strict, wmax, shu, shd);
+    // exclusive offsets of this block (and the survivor total for the last block)
+    const int G = gridDim.x;
+    unsigned long long oq = 0, oc = 0, tc = 0;
+    for (int b = threadIdx.x; b < G; b += kBlock) {
+        const unsigned long long q = a.sc.u1[b], c = a.sc.u2[b];
+        if (b < (int)blockIdx.x) {
+            oq += q;
+            oc += c;
+        }
+        tc += c;
+    }
+    oq = block_sum_u64(oq, shu);
+    oc = block_sum_u64(oc, shu);
+    tc = block_sum_u64(tc, shu);
+    const int k0 = blockIdx.x * kChunk + threadIdx.x * kPer;
+    unsigned long long q[kPer];
+    unsigned long long sq = 0, sc = 0;
+    for (int i = 0; i < kPer; ++i) {
+        const int k = k0 + i;
+        q[i] = k < a.N ? quantise(a.d_prev[k], a.eps, strict, wmax) : 0ull;
+        sq += q[i];
+        sc += q[i] > 0;
+    }
+    unsigned long long tot;
+    unsigned long long run = oq + block_excl_scan_u64(sq, shu, &tot);
+    unsigned long long col = oc + block_excl_scan_u64(sc, shu, &tot);
+    for (int i = 0; i < kPer; ++i) {
+        const int k = k0 + i;
+        if (k >= a.N) break;
+        run += q[i];
+        a.q[k] = q[i];
         a.cdf[k] = run;
-        if (q > 0) {
+        if (q[i] > 0) {
             double* c = a.cols + (size_t)col * 9;
             const double* up = a.u_prev + (size_t)k * kNP;
 #pragma unroll
             for (int dd = 0; dd < kNP; ++dd) c[dd] = up[dd];
-            c[8] = (double)q;
+            c[8] = (double)q[i];
             ++col;
         }
     }
-    if (t == kOne - 1) {
-        a.ctr->survivors = ci;
+    if (blockIdx.x == (unsigned)(G - 1) && threadIdx.x == 0) {
+        a.ctr->survivors = tc;
         a.ctr->fallback = strict ? 0ull : 1ull;
     }
-    (void)nle;
 }
 
 // ---------------------------------------------------------------------------
@@ -136,85 +221,171 @@ __global__ __launch_bounds__(kOne) void resample_kernel(ResampleArgs a)
 // over the previous particles with q_k > 0, and log-weight
 //   l_j = 8 log sigma_j - log L_j,
 // the log of 1 / (proposal density at u_j given sigma_j) up to a constant
-// (prior density 1 on the cube).  One lane per row; column tiles of
+// (prior density 1 on the cube).  One lane per row; the columns are split in
+// `chunks` contiguous ranges (grid y) so the launch fills the chip; tiles of
 // (u_k, q_k) stream through LDS and every lane of the wave reads the same
 // column (broadcast).  Terms whose exponent is below -708 are exactly 0 and
-// skipped; a wave skips the exponential when all its lanes do.  Partial sums
-// per tile are added to the row total (two-level summation).
+// skipped (a wave skips the exponential when all its lanes do).  Two columns
+// are evaluated per iteration into independent accumulators; per-tile and
+// per-chunk partial sums are added in a fixed order.
+//
+// The exponential here is table driven: x = (64 k + i) ln2/64 + r with
+// |r| <= ln2/128, exp(x) = 2^k 2^(i/64) (1 + r + r^2/2 + ... + r^5/5!).  Its
+// relative error (a few 1e-16) is far inside the 1e-12 the weights are held
+// to; the trajectories never use it.
 // ---------------------------------------------------------------------------
 constexpr int kTile = 256;
+
+__device__ __forceinline__ double exp_tab(double x, const double* T, const double* ex)
+{
+    const double kk = __builtin_rint(x * ex[0]);
+    double r = __builtin_fma(-kk, ex[1], x);
+    r = __builtin_fma(-kk, ex[2], r);
+    const int ik = (int)kk;
+    double p = __builtin_fma(ex[6], r, ex[5]);
+    p = __builtin_fma(p, r, ex[4]);
+    p = __builtin_fma(p, r, ex[3]);
+    p = __builtin_fma(p, r, 1.0);
+    p = __builtin_fma(p, r, 1.0);
+    return __builtin_ldexp(T[ik & 63] * p, ik >> 6);
+}
+
+__device__ __forceinline__ double pair_term(const double* uj, double ninv, const double (*tu)[kTile],
+                                            const double* tq, int c, const double* T, const double* ex)
+{
+    double D = 0.0;
+#pragma unroll
+    for (int d = 0; d < kNP; ++d) {
+        const double df = uj[d] - tu[d][c];
+        D = __builtin_fma(df, df, D);
+    }
+    const double arg = D * ninv;
+    return arg >= dm::kExpLo ? tq[c] * exp_tab(arg, T, ex) : 0.0;
+}
 
 __global__ __launch_bounds__(kBlock) void weights_kernel(WeightArgs a)
 {
     __shared__ double tu[kNP][kTile];
     __shared__ double tq[kTile];
+    __shared__ double T[64];
+    if (threadIdx.x < 64) T[threadIdx.x] = dm::exp((double)threadIdx.x * 0.010830424696249145);  // 2^(i/64)
     const int j = blockIdx.x * kBlock + threadIdx.x;
     const bool active = j < a.N;
     double uj[kNP];
-    double ninv = 0.0, sj = 1.0;
+    double ninv = 0.0;
     if (active) {
 #pragma unroll
         for (int d = 0; d < kNP; ++d) uj[d] = a.u[(size_t)j * kNP + d];
-        sj = a.sigma[j];
+        const double sj = a.sigma[j];
         ninv = -1.0 / (2.0 * (sj * sj));
     } else {
 #pragma unroll
         for (int d = 0; d < kNP; ++d) uj[d] = 0.0;
     }
     const int M = (int)*a.M;
+    const int nt = (M + kTile - 1) / kTile;
+    const int S = a.chunks, c = blockIdx.y;
+    const int t0 = (int)(((long long)nt * c) / S), t1 = (int)(((long long)nt * (c + 1)) / S);
     double total = 0.0;
-    for (int c0 = 0; c0 < M; c0 += kTile) {
+    for (int tile = t0; tile < t1; ++tile) {
+        const int c0 = tile * kTile;
         const int n = min(kTile, M - c0);
         __syncthreads();
         if (threadIdx.x < n) {
-            const double* c = a.cols + (size_t)(c0 + threadIdx.x) * 9;
+            const double* col = a.cols + (size_t)(c0 + threadIdx.x) * 9;
 #pragma unroll
-            for (int d = 0; d < kNP; ++d) tu[d][threadIdx.x] = c[d];
-            tq[threadIdx.x] = c[8];
+            for (int d = 0; d < kNP; ++d) tu[d][threadIdx.x] = col[d];
+            tq[threadIdx.x] = col[8];
         }
         __syncthreads();
-        double part = 0.0;
-        for (int c = 0; c < n; ++c) {
-            double D = 0.0;
-#pragma unroll
-            for (int d = 0; d < kNP; ++d) {
-                const double df = uj[d] - tu[d][c];
-                D = __builtin_fma(df, df, D);
-            }
-            const double arg = D * ninv;
-            if (arg >= dm::kExpLo) part = __builtin_fma(tq[c], dm::exp_core(arg), part);
+        double p0 = 0.0, p1 = 0.0;
+        int cc = 0;
+        for (; cc + 1 < n; cc += 2) {
+            p0 += pair_term(uj, ninv, tu, tq, cc, T, a.ex);
+            p1 += pair_term(uj, ninv, tu, tq, cc + 1, T, a.ex);
         }
-        total += part;
+        if (cc < n) p0 += pair_term(uj, ninv, tu, tq, cc, T, a.ex);
+        total += p0 + p1;
     }
-    if (active) a.logw[j] = 8.0 * dm::log(sj) - dm::log(total);
+    if (active) a.partial[(size_t)c * a.N + j] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void weights_finalize_kernel(WeightArgs a)
+{
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= a.N) return;
+    double L = 0.0;
+    for (int c = 0; c < a.chunks; ++c) L += a.partial[(size_t)c * a.N + j];
+    a.logw[j] = 8.0 * dm::log(a.sigma[j]) - dm::log(L);
 }
 
 // ---------------------------------------------------------------------------
-// W_j = exp(l_j - max l) / sum; ESS = 1 / sum W^2.  One workgroup, fixed
-// reduction order (deterministic).
+// W_j = exp(l_j - max l) / sum; ESS = 1 / sum W^2.  Per-block partials
+// combined in block order.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kOne) void normalise_kernel(NormArgs a)
+__global__ __launch_bounds__(kBlock) void norm_max_kernel(NormArgs a)
 {
-    __shared__ double sh[kOne];
-    const int t = threadIdx.x;
+    __shared__ double sh[kBlock];
     double mx = -__builtin_inf();
-    for (int j = t; j < a.N; j += kOne) mx = a.logw[j] > mx ? a.logw[j] : mx;
-    mx = block_reduce_max(mx, sh);
+    for (int i = 0; i < kPer; ++i) {
+        const int j = blockIdx.x * kChunk + i * kBlock + threadIdx.x;
+        if (j < a.N) mx = a.logw[j] > mx ? a.logw[j] : mx;
+    }
+    mx = block_max_f64(mx, sh);
+    if (threadIdx.x == 0) a.sc.d0[blockIdx.x] = mx;
+}
+
+__global__ __launch_bounds__(kBlock) void norm_exp_kernel(NormArgs a)
+{
+    __shared__ double sh[kBlock];
+    double mx = -__builtin_inf();
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) mx = a.sc.d0[b] > mx ? a.sc.d0[b] : mx;
+    mx = block_max_f64(mx, sh);
     double s = 0.0;
-    for (int j = t; j < a.N; j += kOne) {
-        const double e = dm::exp(a.logw[j] - mx);
-        a.W[j] = e;
-        s += e;
+    for (int i = 0; i < kPer; ++i) {
+        const int j = blockIdx.x * kChunk + i * kBlock + threadIdx.x;
+        if (j < a.N) {
+            const double e = dm::exp(a.logw[j] - mx);
+            a.W[j] = e;
+            s += e;
+        }
     }
-    s = block_reduce_sum(s, sh);
+    s = block_sum_f64(s, sh);
+    if (threadIdx.x == 0) a.sc.d1[blockIdx.x] = s;
+}
+
+__device__ __forceinline__ double ordered_total(const double* part, int G, double* sh)
+{
+    // each thread sums a contiguous run of block partials, then a fixed tree
+    const int per = (G + kBlock - 1) / kBlock;
+    double s = 0.0;
+    const int b0 = threadIdx.x * per, b1 = min(G, b0 + per);
+    for (int b = b0; b < b1; ++b) s += part[b];
+    return block_sum_f64(s, sh);
+}
+
+__global__ __launch_bounds__(kBlock) void norm_scale_kernel(NormArgs a)
+{
+    __shared__ double sh[kBlock];
+    const double total = ordered_total(a.sc.d1, gridDim.x, sh);
     double s2 = 0.0;
-    for (int j = t; j < a.N; j += kOne) {
-        const double w = a.W[j] / s;
-        a.W[j] = w;
-        s2 += w * w;
+    for (int i = 0; i < kPer; ++i) {
+        const int j = blockIdx.x * kChunk + i * kBlock + threadIdx.x;
+        if (j < a.N) {
+            const double w = a.W[j] / total;
+            a.W[j] = w;
+            s2 += w * w;
+        }
     }
-    s2 = block_reduce_sum(s2, sh);
-    if (t == 0) *a.ess = 1.0 / s2;
+    s2 = block_sum_f64(s2, sh);
+    if (threadIdx.x == 0) a.sc.d0[blockIdx.x] = s2;
+}
+
+__global__ __launch_bounds__(kBlock) void norm_ess_kernel(NormArgs a, int G)
+{
+    __shared__ double sh[kBlock];
+    const double s2 = ordered_total(a.sc.d0, G, sh);
+    if (threadIdx.x == 0) *a.ess = 1.0 / s2;
 }
 
 __global__ __launch_bounds__(kBlock) void uniform_weights_kernel(double* W, double* logw, int32_t N)
@@ -230,17 +401,19 @@ __global__ __launch_bounds__(kBlock) void uniform_weights_kernel(double* W, doub
 // eq. 8 tolerance: type-7 percentile with numpy's "linear" arithmetic:
 // v = (N-1) alpha, order statistics x_(floor v) and x_(floor v + 1) found by a
 // radix select on the IEEE bit patterns (non-negative doubles order as
-// unsigned integers; digits of 11, 11, 11, 11, 11, 9 bits), then
-// a + (b-a) g, or b - (b-a)(1-g) when g >= 1/2.  One workgroup; the two
-// ranks are selected together.
+// unsigned integers; digits of 11, 11, 11, 11, 11, 9 bits from the top), then
+// a + (b-a) g, or b - (b-a)(1-g) when g >= 1/2.  Per pass: every block
+// histograms its slice in LDS and adds it to the global bins; one block then
+// picks the digit of both ranks.
 // ---------------------------------------------------------------------------
 constexpr int kBins = 2048;
+enum { kPref0 = 0, kPref1, kMask0, kMask1, kRank0, kRank1, kR0, kR1 };
 
-__global__ __launch_bounds__(kOne) void select_kernel(SelectArgs a)
+__device__ __forceinline__ int pass_shift(int pass) { return pass < 5 ? 53 - 11 * pass : 0; }
+__device__ __forceinline__ unsigned long long pass_mask(int pass) { return (1ull << (pass < 5 ? 11 : 9)) - 1ull; }
+
+__global__ __launch_bounds__(kBlock) void select_init_kernel(SelectArgs a)
 {
-    __shared__ unsigned int hist[2][kBins];
-    __shared__ unsigned long long s_pref[2], s_mask[2], s_rank[2];
-    const int t = threadIdx.x;
     const int N = a.N;
     const double v = ((double)N - 1.0) * a.alpha;
     long long r0, r1;
@@ -252,49 +425,87 @@ __global__ __launch_bounds__(kOne) void select_kernel(SelectArgs a)
         r0 = (long long)__builtin_floor(v);
         r1 = r0 + 1;
     }
-    if (t < 2) {
-        s_pref[t] = 0;
-        s_mask[t] = 0;
-        s_rank[t] = (unsigned long long)(t == 0 ? r0 : r1);
+    for (int b = threadIdx.x; b < 2 * kBins; b += kBlock) a.sc.hist[b] = 0u;
+    if (threadIdx.x == 0) {
+        unsigned long long* st = a.sc.sel;
+        st[kPref0] = st[kPref1] = st[kMask0] = st[kMask1] = 0ull;
+        st[kRank0] = (unsigned long long)r0;
+        st[kRank1] = (unsigned long long)r1;
+        st[kR0] = (unsigned long long)r0;
+        st[kR1] = (unsigned long long)r1;
     }
-    for (int pass = 0; pass < 6; ++pass) {
-        for (int b = t; b < 2 * kBins; b += kOne) (&hist[0][0])[b] = 0;
-        __syncthreads();
-        const int sh = pass < 5 ? 53 - 11 * pass : 0;
-        const unsigned long long dmask = (1ull << (pass < 5 ? 11 : 9)) - 1ull;
-        const unsigned long long p0 = s_pref[0], m0 = s_mask[0], p1 = s_pref[1], m1 = s_mask[1];
-        for (int k = t; k < N; k += kOne) {
-            const unsigned long long bits = (unsigned long long)__double_as_longlong(a.x[k]);
-            const unsigned int dig = (unsigned int)((bits >> sh) & dmask);
-            if ((bits & m0) == p0) atomicAdd(&hist[0][dig], 1u);
-            if ((bits & m1) == p1) atomicAdd(&hist[1][dig], 1u);
-        }
-        __syncthreads();
-        if (t < 2) {
-            unsigned long long rem = s_rank[t], cum = 0;
-            int b = 0;
-            for (; b < (int)(dmask + 1); ++b) {
-                if (cum + hist[t][b] > rem) break;
-                cum += hist[t][b];
+}
+
+__global__ __launch_bounds__(kBlock) void select_hist_kernel(SelectArgs a, int pass)
+{
+    __shared__ unsigned int h[2][kBins];
+    for (int b = threadIdx.x; b < 2 * kBins; b += kBlock) (&h[0][0])[b] = 0u;
+    __syncthreads();
+    const unsigned long long* st = a.sc.sel;
+    const unsigned long long p0 = st[kPref0], p1 = st[kPref1], m0 = st[kMask0], m1 = st[kMask1];
+    const int sh = pass_shift(pass);
+    const unsigned long long dmk = pass_mask(pass);
+    for (int k = blockIdx.x * kBlock + threadIdx.x; k < a.N; k += gridDim.x * kBlock) {
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(a.x[k]);
+        const unsigned int dig = (unsigned int)((bits >> sh) & dmk);
+        if ((bits & m0) == p0) atomicAdd(&h[0][dig], 1u);
+        if ((bits & m1) == p1) atomicAdd(&h[1][dig], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < 2 * kBins; b += kBlock) {
+        const unsigned int v = (&h[0][0])[b];
+        if (v) atomicAdd(&a.sc.hist[b], v);
+    }
+}
+
+// One block: for each rank find the bin whose cumulative count passes it.
+__global__ __launch_bounds__(kBlock) void select_pick_kernel(SelectArgs a, int pass)
+{
+    __shared__ unsigned long long part[kBlock];
+    __shared__ unsigned long long s_bin[2], s_below[2];
+    unsigned long long* st = a.sc.sel;
+    const int sh = pass_shift(pass);
+    const int nb = (int)pass_mask(pass) + 1;
+    const int per = (nb + kBlock - 1) / kBlock;  // contiguous bins per thread
+    for (int which = 0; which < 2; ++which) {
+        const unsigned int* h = a.sc.hist + which * kBins;
+        const unsigned long long rank = st[kRank0 + which];
+        const int b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
+        unsigned long long s = 0;
+        for (int b = b0; b < b1; ++b) s += h[b];
+        unsigned long long tot;
+        unsigned long long run = block_excl_scan_u64(s, part, &tot);
+        // the thread whose run contains the rank locates the bin
+        for (int b = b0; b < b1; ++b) {
+            if (run <= rank && rank < run + h[b]) {
+                s_bin[which] = (unsigned long long)b;
+                s_below[which] = run;
             }
-            s_rank[t] = rem - cum;
-            s_pref[t] |= (unsigned long long)b << sh;
-            s_mask[t] |= dmask << sh;
+            run += h[b];
         }
         __syncthreads();
     }
-    if (t == 0) {
-        const double xa = __longlong_as_double((long long)s_pref[0]);
-        const double xb = __longlong_as_double((long long)s_pref[1]);
-        double res;
-        if (r0 == r1) {
-            res = xa;
-        } else {
-            const double g = v - __builtin_floor(v);
-            const double diff = xb - xa;
-            res = g >= 0.5 ? xb - diff * (1.0 - g) : xa + diff * g;
+    for (int b = threadIdx.x; b < 2 * kBins; b += kBlock) a.sc.hist[b] = 0u;
+    if (threadIdx.x == 0) {
+        for (int which = 0; which < 2; ++which) {
+            st[kRank0 + which] -= s_below[which];
+            st[kPref0 + which] |= s_bin[which] << sh;
+            st[kMask0 + which] |= pass_mask(pass) << sh;
         }
-        *a.out = res;
+        if (pass == 5) {
+            const double xa = __longlong_as_double((long long)st[kPref0]);
+            const double xb = __longlong_as_double((long long)st[kPref1]);
+            double res;
+            if (st[kR0] == st[kR1]) {
+                res = xa;
+            } else {
+                const double v = ((double)a.N - 1.0) * a.alpha;
+                const double g = v - __builtin_floor(v);
+                const double diff = xb - xa;
+                res = g >= 0.5 ? xb - diff * (1.0 - g) : xa + diff * g;
+            }
+            *a.out = res;
+        }
     }
 }
 
@@ -307,38 +518,74 @@ __global__ __launch_bounds__(kBlock) void to_theta_kernel(const double* u, Model
     theta[i] = m.lo[d] + u[i] * m.width[d];
 }
 
+inline unsigned blocks_of(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
 }  // namespace
+
+void weight_exp_constants(double ex[7])
+{
+    ex[0] = 92.332482616893658;           // 64 / ln 2
+    ex[1] = dm::kLn2Hi / 64.0;            // exact scaling of the two-part ln 2
+    ex[2] = dm::kLn2Lo / 64.0;
+    ex[3] = 1.0 / 2.0;
+    ex[4] = 1.0 / 6.0;
+    ex[5] = 1.0 / 24.0;
+    ex[6] = 1.0 / 120.0;
+}
+
+int weight_chunks(int64_t N)
+{
+    const int64_t row_blocks = (N + kBlock - 1) / kBlock;
+    int64_t S = (2048 + row_blocks - 1) / row_blocks;
+    const int64_t cap = ((int64_t)1 << 23) / N;
+    if (S > cap) S = cap;
+    if (S > 64) S = 64;
+    if (S < 1) S = 1;
+    return (int)S;
+}
 
 void launch_to_theta(const double* u, const Model& m, double* theta, int64_t n, hipStream_t s)
 {
-    hipLaunchKernelGGL(to_theta_kernel, dim3((unsigned)((n * kNP + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       u, m, theta, n);
+    hipLaunchKernelGGL(to_theta_kernel, dim3(blocks_of(n * kNP, kBlock)), dim3(kBlock), 0, s, u, m, theta, n);
 }
 
 void launch_resample(const ResampleArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(resample_kernel, dim3(1), dim3(kOne), 0, s, a);
+    const dim3 g(blocks_of(a.N, kChunk)), b(kBlock);
+    hipLaunchKernelGGL(resample_stats_kernel, g, b, 0, s, a);
+    hipLaunchKernelGGL(resample_count_kernel, g, b, 0, s, a);
+    hipLaunchKernelGGL(resample_write_kernel, g, b, 0, s, a);
 }
 
 void launch_weights(const WeightArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(weights_kernel, dim3((a.N + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(weights_kernel, dim3(blocks_of(a.N, kBlock), a.chunks), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(weights_finalize_kernel, dim3(blocks_of(a.N, kBlock)), dim3(kBlock), 0, s, a);
 }
 
 void launch_normalise(const NormArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(normalise_kernel, dim3(1), dim3(kOne), 0, s, a);
+    const unsigned G = blocks_of(a.N, kChunk);
+    hipLaunchKernelGGL(norm_max_kernel, dim3(G), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(norm_exp_kernel, dim3(G), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(norm_scale_kernel, dim3(G), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(norm_ess_kernel, dim3(1), dim3(kBlock), 0, s, a, (int)G);
 }
 
 void launch_uniform_weights(double* W, double* logw, int32_t N, hipStream_t s)
 {
-    hipLaunchKernelGGL(uniform_weights_kernel, dim3((N + kBlock - 1) / kBlock), dim3(kBlock), 0, s, W,
-                       logw, N);
+    hipLaunchKernelGGL(uniform_weights_kernel, dim3(blocks_of(N, kBlock)), dim3(kBlock), 0, s, W, logw, N);
 }
 
 void launch_select(const SelectArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kOne), 0, s, a);
+    unsigned G = blocks_of(a.N, 4 * kBlock);
+    if (G > 1024) G = 1024;
+    hipLaunchKernelGGL(select_init_kernel, dim3(1), dim3(kBlock), 0, s, a);
+    for (int pass = 0; pass < 6; ++pass) {
+        hipLaunchKernelGGL(select_hist_kernel, dim3(G), dim3(kBlock), 0, s, a, pass);
+        hipLaunchKernelGGL(select_pick_kernel, dim3(1), dim3(kBlock), 0, s, a, pass);
+    }
 }
 
 }  // namespace abcsmc

@@ -1,0 +1,110 @@
+"""Parity at the benchmark's sizes and launch configuration (torch
+workspace and stream, early exit on, library-chosen batches).
+
+C2 (P=1e7, T=120, N=131072): stages 0 and 1 are recomputed completely by the
+oracle (process pool) and compared bit for bit, including eps^1 and eps^2;
+importance weights on sampled rows within 1e-12.  C3 (P=3e8, T=180,
+N=2^20): sampled stage-0 particles bit for bit, invariants of stage 1."""
+import numpy as np
+import pytest
+
+from paper_2106_15508_amd import abcsmc as A
+from paper_2106_15508_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _bits(x):
+    return np.ascontiguousarray(x, dtype=np.float64).view(np.uint64)
+
+
+def _gpu_stages(w, obs, stages):
+    import torch
+    ws_tensor, ws = A.torch_workspace(w)
+    stream = torch.cuda.current_stream()
+    out = []
+    with A.Context(w, obs, stream=stream.cuda_stream, workspace=ws, flags=A.F_EARLY_EXIT) as ctx:
+        for i in range(stages):
+            info = ctx.round()
+            pop = ctx.population()
+            _, d, wt = ctx.weights()
+            pop["d"], pop["W"], pop["info"] = d, wt, info
+            if i >= 1:
+                pop["q"], pop["cdf"] = ctx.resampling()
+            out.append(pop)
+    torch.cuda.synchronize()
+    del ws_tensor
+    return out
+
+
+def test_c2_stages_0_1_bitwise(oracle):
+    from oracle import parallel
+    w = W.C2
+    N = w.n_particles
+    obs = oracle.observations(w)
+    g = _gpu_stages(w, obs, 2)
+
+    # stage 0: all N particles
+    u0, d0 = parallel.stage0(w, obs, N)
+    assert np.array_equal(g[0]["index"], np.arange(N))
+    assert np.array_equal(_bits(g[0]["u"]), _bits(u0))
+    assert np.array_equal(_bits(g[0]["d"]), _bits(d0))
+    eps1 = oracle.quantile(d0, w.surv_ratio)
+    assert _bits([g[0]["info"]["eps_next"]])[0] == _bits([eps1])[0]
+
+    # stage 1: every proposal up to the N-th acceptance
+    q, cdf, _ = oracle.resample_weights(d0, eps1)
+    assert np.array_equal(g[1]["q"], q) and np.array_equal(g[1]["cdf"], cdf)
+    n_prop = g[1]["info"]["proposals"]
+    res = parallel.stage(w, obs, 1, u0, cdf, 1.0, 2, range(n_prop))
+    acc = [r for r in res if r[1] > 0 and r[5] <= eps1]
+    assert len(acc) == N                      # the N-th acceptance is the last proposal
+    assert acc[-1][0] == n_prop - 1
+    idx = np.array([r[0] for r in acc])
+    assert np.array_equal(g[1]["index"], idx)
+    assert np.array_equal(_bits(g[1]["u"]), _bits(np.stack([r[2] for r in acc])))
+    assert np.array_equal(_bits(g[1]["sigma"]), _bits(np.array([r[3] for r in acc])))
+    assert np.array_equal(g[1]["parent"], np.array([r[4] for r in acc]))
+    assert np.array_equal(g[1]["attempts"], np.array([r[1] for r in acc]))
+    d1 = np.array([r[5] for r in acc])
+    assert np.array_equal(_bits(g[1]["d"]), _bits(d1))
+    eps2 = oracle.quantile(d1, w.surv_ratio)
+    assert _bits([g[1]["info"]["eps_next"]])[0] == _bits([eps2])[0]
+
+    # importance weights on sampled rows (unnormalised log-weights) and normalisation
+    rows = np.unique(np.concatenate([[0, N - 1], np.random.default_rng(1).integers(0, N, 96)]))
+    for k in rows:
+        want = oracle.log_weight(acc[k][2], acc[k][3], u0, q)   # the oracle's own particle k
+        assert abs(g[1]["logw"][k] - want) <= 1e-12 * max(1.0, abs(want)), k
+    assert abs(g[1]["W"].sum() - 1.0) < 1e-12
+    assert np.all(g[1]["W"] >= 0)
+
+
+def test_c3_sampled_and_invariants(oracle):
+    w = W.C3
+    N = w.n_particles
+    obs = oracle.observations(w)
+    g = _gpu_stages(w, obs, 2)
+    rng = np.random.default_rng(3)
+    for j in np.unique(np.concatenate([[0, 1, N - 1], rng.integers(0, N, 200)])):
+        u = oracle.prior_draw(w, int(j))
+        assert np.array_equal(_bits(g[0]["u"][j]), _bits(u)), j
+        assert _bits([g[0]["d"][j]])[0] == _bits([oracle.sim_distance(w, obs, u, 0, int(j))])[0], j
+    # eps^1 is the linear-interpolation median of the stage-0 distances (numpy)
+    assert g[0]["info"]["eps_next"] == np.quantile(g[0]["d"], w.surv_ratio, method="linear")
+    st = g[1]
+    eps1 = st["info"]["eps"]
+    assert np.all(st["d"] <= eps1)
+    assert np.all(np.diff(st["index"]) > 0)
+    assert st["index"][-1] == st["info"]["proposals"] - 1
+    assert np.all((st["u"] >= 0) & (st["u"] <= 1))
+    assert abs(st["W"].sum() - 1.0) < 1e-12
+    assert st["info"]["eps_next"] == np.quantile(st["d"], w.surv_ratio, method="linear")
+    # the integer CDF is the running sum of the quantised eq. 10 weights: zero
+    # outside the prior set d < eps^1, largest weight exactly 2^40
+    q, cdf = st["q"], st["cdf"]
+    d0 = g[0]["d"]
+    assert np.all(q[d0 >= eps1] == 0) and np.all(q[d0 < eps1] <= 2**40)
+    assert q.max() == 2**40 and q[np.argmin(d0)] == 2**40
+    assert np.array_equal(cdf, np.cumsum(q.astype(object)).astype(np.uint64))
+    assert st["info"]["survivors"] == int(np.count_nonzero(q))

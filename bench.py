@@ -61,7 +61,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"],
+                    help="c4: 96 uneven runs in the batched mode, compared with the same runs one at a time")
+    ap.add_argument("--runs", type=int, default=96, help="c4: number of runs")
     ap.add_argument("--early-exit", type=int, default=1, help="stop simulating a proposal once its "
                     "partial distance exceeds eps (acceptances unchanged)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
@@ -123,6 +125,68 @@ def cpu_baseline(w, infos, budget_s: float):
     }
 
 
+def bench_batched(args):
+    """96 independent runs (populations log-uniform in [1e5, 3e8], 40-150
+    days, N in {2^11..2^16}) advanced together by the batched mode (one graph
+    replay per stage), against the same runs one after another."""
+    import torch
+
+    from paper_2106_15508_amd import abcsmc as A
+    from paper_2106_15508_amd import workloads as W
+
+    runs = W.batched_runs(n_runs=args.runs, seed=4, n_rounds=10)
+    R = runs[0].n_rounds
+    obs = [A.observations(w) for w in runs]
+    flags = A.F_EARLY_EXIT if args.early_exit else 0
+    stream = torch.cuda.Stream()
+    nbytes = A.Batch.workspace_size(runs, flags=flags)
+    ws_tensor = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    ws = ((ws_tensor.data_ptr() + 255) // 256 * 256, nbytes)
+    b = A.Batch(runs, obs, stream=stream.cuda_stream, workspace=ws, flags=flags)
+    t0 = time.perf_counter()
+    sched = b.autotune(stages=1)
+    tune_s = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        b.reset()
+        b.run(R)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.reset()
+        infos = b.run(R)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    accepted = sum(w.n_particles for w in runs) * R
+    simulated = sum(i["simulated"] for st in infos for i in st)
+    failed = [r for r in range(len(runs)) if b.status(r) != A.OK]
+    b.close()
+    # the same runs one at a time (library-chosen batches, same flags)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for w, o in zip(runs, obs):
+        with A.Context(w, o, flags=flags) as ctx:
+            ctx.run(R)
+    torch.cuda.synchronize()
+    sec_plain = time.perf_counter() - t0
+    out = {
+        "metric": "accepted particles/s", "value": accepted / sec, "unit": "accepted particles/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"c4: {len(runs)} independent runs, P log-uniform in [1e5, 3e8], T in [40, 150], "
+                               f"N in {{2^11..2^16}} (sum N = {sum(w.n_particles for w in runs)}), {R} stages, "
+                               "batched mode (one graph replay per stage)",
+                   "early_exit": bool(args.early_exit), "schedule": sched, "autotune_s": round(tune_s, 2)},
+        "simulations_per_s": simulated / sec,
+        "plain_sequential_value": accepted / sec_plain,
+        "speedup_vs_plain": sec_plain / sec,
+        "failed_runs": failed,
+        "roofline": None,
+    }
+    del ws_tensor
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -136,6 +200,8 @@ def main():
     from paper_2106_15508_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.workload == "c4":
+        return bench_batched(args)
     if args.calibrate_copy:
         src = torch.ones(args.calibrate_copy, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

@@ -178,6 +178,55 @@ int abcsmc_simulate(const abcsmc_config* cfg, int64_t n, const double* theta, co
  *  fn 12: floor-normal draw                                 (in: {int64 n, double h, uint64 w}[n]; out: int64[n]) */
 int abcsmc_debug_eval(int32_t fn, int64_t n, const void* in, void* out, double param_a, int32_t param_b);
 
+/* ---------------------------------------------------------------------------
+ * Batched mode: many independent runs (own population, horizon, particle
+ * count, seed, observations, step law) advanced one stage at a time by one
+ * captured graph per stage: segmented resampling, one persistent proposal
+ * kernel that hands out (run, 256-proposal chunk) work items to every
+ * workgroup, per-run ordered compaction, segmented importance weights,
+ * per-run percentile.  Each run's trajectories, distances, acceptances and
+ * tolerances are bit-identical to the same run alone (abcsmc_init/round);
+ * weights agree to 1e-12.  A run that exhausts its per-stage proposal capacity
+ * (cfg.max_proposals, default max(4 N, 16384)) stops with ABCSMC_EBUDGET and
+ * keeps its last completed stage while the others continue.
+ * Stream and workspace come from cfgs[0]; cfgs[r].batch is ignored.
+ * ------------------------------------------------------------------------- */
+typedef struct abcsmc_batch abcsmc_batch;
+
+/* Launch schedule of the batched mode (no result depends on it). */
+typedef struct {
+    int32_t propose_blocks;  /* workgroups of the persistent proposal kernel; 0 = 2 per CU */
+    int32_t run_order;       /* order runs are offered to workgroups: 0 index, 1 largest N*T first,
+                                2 largest/smallest interleaved */
+    int32_t weight_cols;     /* target columns per weight-kernel workgroup (0 = 4096) */
+    double issue_margin;     /* chunk budget N / (rate * 256) x margin before over-issue (0 = 1.1) */
+} abcsmc_schedule;
+
+int abcsmc_batch_workspace_size(const abcsmc_config* cfgs, int32_t n_runs, size_t* bytes);
+/* obs[r]: (T_r+1) x 3 int64 of run r; copied.  1 <= n_runs <= 4096, N_r <= 2^20. */
+int abcsmc_batch_init(const abcsmc_config* cfgs, int32_t n_runs, const int64_t* const* obs, abcsmc_batch** out);
+int abcsmc_batch_set_schedule(abcsmc_batch* b, const abcsmc_schedule* s);
+int abcsmc_batch_get_schedule(const abcsmc_batch* b, abcsmc_schedule* s);
+/* Time schedule variants (coordinate descent over the four knobs, each trial
+ * = stage 0 plus `stages` stages from a reset) and keep the fastest; a line
+ * per batch shape is appended to / looked up in cache_path (NULL: no cache).
+ * Leaves the batch reset at stage 0. */
+int abcsmc_batch_autotune(abcsmc_batch* b, int32_t stages, const char* cache_path, abcsmc_schedule* chosen);
+/* Next stage of every run (one graph replay).  infos: n_runs entries or NULL. */
+int abcsmc_batch_round(abcsmc_batch* b, abcsmc_round_info* infos);
+/* n_rounds stages; infos: n_rounds x n_runs entries (stage-major) or NULL. */
+int abcsmc_batch_run(abcsmc_batch* b, int32_t n_rounds, abcsmc_round_info* infos);
+int abcsmc_batch_reset(abcsmc_batch* b);
+/* 0, or ABCSMC_EBUDGET once run r has stopped. */
+int abcsmc_batch_status(const abcsmc_batch* b, int32_t run);
+int abcsmc_batch_rounds_done(const abcsmc_batch* b, int32_t run);
+/* Last completed stage of run r (any pointer may be NULL); layouts as abcsmc_population /
+ * abcsmc_weights (u in unit-cube coordinates). */
+int abcsmc_batch_population(const abcsmc_batch* b, int32_t run, double* u, double* sigma, int64_t* parent,
+                            int64_t* index, int32_t* attempts, double* logw, double* dist, double* weight);
+void abcsmc_batch_free(abcsmc_batch* b); /* NULL-safe */
+const char* abcsmc_batch_last_error(const abcsmc_batch* b);
+
 void abcsmc_free(abcsmc_ctx* ctx); /* NULL-safe */
 const char* abcsmc_strerror(int code);
 const char* abcsmc_last_error(const abcsmc_ctx* ctx); /* NULL ctx: last error of a context-less call */

@@ -30,6 +30,10 @@ EXPORTS = (
     "abcsmc_workspace_size", "abcsmc_init", "abcsmc_round", "abcsmc_weights", "abcsmc_population",
     "abcsmc_resampling", "abcsmc_reset", "abcsmc_rounds_done", "abcsmc_run", "abcsmc_simulate", "abcsmc_debug_eval",
     "abcsmc_free", "abcsmc_strerror", "abcsmc_last_error", "abcsmc_abi_version",
+    "abcsmc_batch_workspace_size", "abcsmc_batch_init", "abcsmc_batch_set_schedule",
+    "abcsmc_batch_get_schedule", "abcsmc_batch_autotune", "abcsmc_batch_round", "abcsmc_batch_run",
+    "abcsmc_batch_reset", "abcsmc_batch_status", "abcsmc_batch_rounds_done", "abcsmc_batch_population",
+    "abcsmc_batch_free", "abcsmc_batch_last_error",
 )
 
 
@@ -50,6 +54,14 @@ class Config(C.Structure):
         ("max_proposals", C.c_int64), ("stream", C.c_void_p), ("workspace", C.c_void_p),
         ("workspace_bytes", C.c_size_t),
     ]
+
+
+class Schedule(C.Structure):
+    _fields_ = [("propose_blocks", C.c_int32), ("run_order", C.c_int32), ("weight_cols", C.c_int32),
+                ("issue_margin", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class RoundInfo(C.Structure):
@@ -78,6 +90,13 @@ def load(path: Optional[str] = None):
     path = path or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} (run python -m paper_2106_15508_amd.build)")
+    # One HIP runtime per process: when PyTorch is installed its bundled
+    # runtime must be the one loaded first (same soname), otherwise torch
+    # cannot initialise the device later in the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(path, mode=os.RTLD_LOCAL)
     vp, i32, i64, u32, u64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
     sig = {
@@ -96,6 +115,19 @@ def load(path: Optional[str] = None):
         "abcsmc_strerror": (C.c_char_p, [C.c_int]),
         "abcsmc_last_error": (C.c_char_p, [vp]),
         "abcsmc_abi_version": (C.c_int, []),
+        "abcsmc_batch_workspace_size": (C.c_int, [vp, i32, vp]),
+        "abcsmc_batch_init": (C.c_int, [vp, i32, vp, vp]),
+        "abcsmc_batch_set_schedule": (C.c_int, [vp, vp]),
+        "abcsmc_batch_get_schedule": (C.c_int, [vp, vp]),
+        "abcsmc_batch_autotune": (C.c_int, [vp, i32, C.c_char_p, vp]),
+        "abcsmc_batch_round": (C.c_int, [vp, vp]),
+        "abcsmc_batch_run": (C.c_int, [vp, i32, vp]),
+        "abcsmc_batch_reset": (C.c_int, [vp]),
+        "abcsmc_batch_status": (C.c_int, [vp, i32]),
+        "abcsmc_batch_rounds_done": (C.c_int, [vp, i32]),
+        "abcsmc_batch_population": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "abcsmc_batch_free": (None, [vp]),
+        "abcsmc_batch_last_error": (C.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -270,3 +302,97 @@ def torch_workspace(w: W.Workload, device: str = "cuda", **kw):
     t = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
     ptr = (t.data_ptr() + 255) // 256 * 256
     return t, (ptr, nbytes)
+
+
+def _bcheck(rc: int, b=None):
+    if rc != OK:
+        L = load()
+        msg = L.abcsmc_batch_last_error(b).decode()
+        raise AbcsmcError(rc, msg or L.abcsmc_strerror(rc).decode())
+
+
+class Batch:
+    """Many independent runs advanced together (abcsmc_batch_*)."""
+
+    def __init__(self, workloads: Sequence[W.Workload], obs_list, *, stream=None, workspace=None,
+                 flags: int = 0):
+        self.ws = list(workloads)
+        self.R = len(self.ws)
+        cfgs = (Config * self.R)()
+        for r, w in enumerate(self.ws):
+            cfgs[r] = make_config(w, stream=stream if r == 0 else None,
+                                  workspace=workspace if r == 0 else None, flags=flags)
+        self._cfgs = cfgs
+        self._obs = [np.ascontiguousarray(o, dtype=np.int64) for o in obs_list]
+        ptrs = (C.c_void_p * self.R)(*[o.ctypes.data for o in self._obs])
+        self._h = C.c_void_p()
+        self.L = load()
+        _bcheck(self.L.abcsmc_batch_init(cfgs, self.R, ptrs, C.byref(self._h)))
+
+    @staticmethod
+    def workspace_size(workloads, flags: int = 0) -> int:
+        R = len(workloads)
+        cfgs = (Config * R)()
+        for r, w in enumerate(workloads):
+            cfgs[r] = make_config(w, flags=flags)
+        n = C.c_size_t()
+        _bcheck(load().abcsmc_batch_workspace_size(cfgs, R, C.byref(n)))
+        return n.value
+
+    def set_schedule(self, propose_blocks=0, run_order=1, weight_cols=0, issue_margin=0.0):
+        s = Schedule(propose_blocks, run_order, weight_cols, issue_margin)
+        _bcheck(self.L.abcsmc_batch_set_schedule(self._h, C.byref(s)), self._h)
+
+    def schedule(self) -> dict:
+        s = Schedule()
+        _bcheck(self.L.abcsmc_batch_get_schedule(self._h, C.byref(s)), self._h)
+        return s.as_dict()
+
+    def autotune(self, stages: int = 2, cache_path: Optional[str] = None) -> dict:
+        s = Schedule()
+        cp = cache_path.encode() if cache_path else None
+        _bcheck(self.L.abcsmc_batch_autotune(self._h, stages, cp, C.byref(s)), self._h)
+        return s.as_dict()
+
+    def round(self) -> List[dict]:
+        infos = (RoundInfo * self.R)()
+        _bcheck(self.L.abcsmc_batch_round(self._h, infos), self._h)
+        return [i.as_dict() for i in infos]
+
+    def run(self, n_rounds: int) -> List[List[dict]]:
+        return [self.round() for _ in range(n_rounds)]
+
+    def reset(self):
+        _bcheck(self.L.abcsmc_batch_reset(self._h), self._h)
+
+    def status(self, r: int) -> int:
+        return self.L.abcsmc_batch_status(self._h, r)
+
+    def rounds_done(self, r: int) -> int:
+        return self.L.abcsmc_batch_rounds_done(self._h, r)
+
+    def population(self, r: int) -> dict:
+        N = self.ws[r].n_particles
+        out = dict(u=np.zeros((N, 8)), sigma=np.zeros(N), parent=np.zeros(N, np.int64),
+                   index=np.zeros(N, np.int64), attempts=np.zeros(N, np.int32), logw=np.zeros(N),
+                   d=np.zeros(N), W=np.zeros(N))
+        _bcheck(self.L.abcsmc_batch_population(self._h, r, *(_p(out[k]) for k in
+                ("u", "sigma", "parent", "index", "attempts", "logw", "d", "W"))), self._h)
+        return out
+
+    def close(self):
+        if self._h:
+            self.L.abcsmc_batch_free(self._h)
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

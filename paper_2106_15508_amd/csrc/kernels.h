@@ -120,6 +120,18 @@ struct WeightArgs {
     const unsigned long long* M;  // device scalar: survivors
     double* partial;        // chunks x N row sums per column chunk
     double* logw;           // N
+    // windowed evaluation: columns sorted by one coordinate, rows by
+    // (step-size octave, same coordinate); each workgroup visits only the
+    // columns that can give a nonzero term
+    unsigned long long* rowkeys;  // Npad sort keys (row index in the low 32 bits)
+    unsigned long long* colkeys;  // Npad sort keys (column index in the low 32 bits)
+    double* scols;          // M x 9 columns in sorted order
+    double* skey;           // M sorted coordinate values
+    double* dimpart;        // per-block partial sums for the coordinate choice (kRedMax x 16)
+    int32_t* dstar;         // device scalar: the coordinate
+    size_t npad;            // padded sort length (power of two >= N)
+    int2* win;              // per row block: sorted column range [first, end) of its window
+    int32_t cols_per_chunk; // columns per grid-y chunk of a window
     // exp by table: 64/ln2, ln2/64 (hi, lo), Taylor 1/2!, 1/3!, 1/4!, 1/5! (kernel
     // arguments so they sit in scalar registers)
     double ex[7];
@@ -127,6 +139,10 @@ struct WeightArgs {
 
 // Fill WeightArgs::ex.
 void weight_exp_constants(double ex[7]);
+
+// Bitonic sort of 64-bit keys (length a power of two >= 2048).
+size_t sort_padded_size(size_t n);
+void launch_sort_u64(unsigned long long* keys, size_t n_pow2, hipStream_t s);
 
 struct NormArgs {
     const double* logw;
@@ -147,6 +163,9 @@ struct SelectArgs {
 // Column chunks of the weight kernel for N rows: enough workgroups to give
 // every SIMD about eight waves, with the partial sums bounded by 2^23 doubles.
 int weight_chunks(int64_t N);
+// Windowed weight kernel: columns per chunk and chunks per row block.
+int weight_cols_per_chunk(int64_t N);
+int weight_window_chunks(int64_t N);
 
 struct TrajArgs {
     Model m;

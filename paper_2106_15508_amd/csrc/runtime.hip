@@ -35,7 +35,7 @@ struct DevPop {
 // Byte layout of the device workspace (every region 256-byte aligned).
 struct Layout {
     size_t obs, pop[2][8], q, cdf, cols, st_u, st_d, st_sigma, st_parent, st_att, wave_mask, wave_off,
-        ctr, scal, theta, red[5], hist, sel, wpart, total;
+        ctr, scal, theta, red[5], hist, sel, wpart, rowkeys, colkeys, scols, skey, dimpart, dstar, win, total;
 };
 
 constexpr size_t kAlign = 256;
@@ -93,7 +93,15 @@ Layout make_layout(const abcsmc_config& c)
     for (int r = 0; r < 5; ++r) L.red[r] = take(kRedMax * 8);
     L.hist = take(2 * 2048 * sizeof(unsigned int));
     L.sel = take(8 * sizeof(unsigned long long));
-    L.wpart = take((size_t)weight_chunks((int64_t)N) * N * sizeof(double));
+    L.wpart = take((size_t)std::max(weight_chunks((int64_t)N), weight_window_chunks((int64_t)N)) * N * sizeof(double));
+    const size_t npad = sort_padded_size(N);
+    L.rowkeys = take(npad * 8);
+    L.colkeys = take(npad * 8);
+    L.scols = take(N * 9 * sizeof(double));
+    L.skey = take(N * sizeof(double));
+    L.dimpart = take(256 * 16 * sizeof(double));
+    L.dstar = take(sizeof(int32_t));
+    L.win = take(((N + kBlock - 1) / kBlock) * sizeof(int2));
     L.total = o;
     return L;
 }
@@ -464,8 +472,24 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
     if (r == 0) {
         launch_uniform_weights(dst.W, dst.logw, N, s);
     } else {
-        WeightArgs wa{dst.u, dst.sigma, x->at<double>(x->L.cols), N, weight_chunks(N), &ctr->survivors,
-                      x->at<double>(x->L.wpart), dst.logw, {}};
+        WeightArgs wa{};
+        wa.u = dst.u;
+        wa.sigma = dst.sigma;
+        wa.cols = x->at<double>(x->L.cols);
+        wa.N = N;
+        wa.chunks = weight_window_chunks(N);
+        wa.cols_per_chunk = weight_cols_per_chunk(N);
+        wa.win = x->at<int2>(x->L.win);
+        wa.M = &ctr->survivors;
+        wa.partial = x->at<double>(x->L.wpart);
+        wa.logw = dst.logw;
+        wa.rowkeys = x->at<unsigned long long>(x->L.rowkeys);
+        wa.colkeys = x->at<unsigned long long>(x->L.colkeys);
+        wa.scols = x->at<double>(x->L.scols);
+        wa.skey = x->at<double>(x->L.skey);
+        wa.dimpart = x->at<double>(x->L.dimpart);
+        wa.dstar = x->at<int32_t>(x->L.dstar);
+        wa.npad = sort_padded_size((size_t)N);
         weight_exp_constants(wa.ex);
         HIPCHK(x, hipEventRecord(x->ev[7], s));
         launch_weights(wa, s);

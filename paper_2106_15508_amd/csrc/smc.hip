@@ -7,6 +7,7 @@
 // is bitwise reproducible run to run.
 #include "dmath.h"
 #include "kernels.h"
+#include "wterm.h"
 
 namespace abcsmc {
 
@@ -234,70 +235,226 @@ __global__ __launch_bounds__(kBlock) void resample_write_kernel(ResampleArgs a)
 // relative error (a few 1e-16) is far inside the 1e-12 the weights are held
 // to; the trajectories never use it.
 // ---------------------------------------------------------------------------
-constexpr int kTile = 256;
+using wterm::kTile;
+using wterm::pair_term;
 
-__device__ __forceinline__ double exp_tab(double x, const double* T, const double* ex)
-{
-    const double kk = __builtin_rint(x * ex[0]);
-    double r = __builtin_fma(-kk, ex[1], x);
-    r = __builtin_fma(-kk, ex[2], r);
-    const int ik = (int)kk;
-    double p = __builtin_fma(ex[6], r, ex[5]);
-    p = __builtin_fma(p, r, ex[4]);
-    p = __builtin_fma(p, r, ex[3]);
-    p = __builtin_fma(p, r, 1.0);
-    p = __builtin_fma(p, r, 1.0);
-    return __builtin_ldexp(T[ik & 63] * p, ik >> 6);
-}
+// ---- windowed evaluation -------------------------------------------------
+// A term is exactly zero (exponent below -708) once |u_jd - u_kd| exceeds
+// sqrt(1416) sigma_j in any one coordinate d; with R_j = 37.7 sigma_j (0.4%
+// above that bound) every column outside [u_jd - R_j, u_jd + R_j] contributes
+// exactly 0, in the oracle's sum as here.  Per stage: pick the coordinate d*
+// with the largest spread among the columns (the window then excludes the
+// most columns: sigma is the same in every coordinate), sort the columns by it, sort
+// the rows by (octave of sigma, u_d*), and let every workgroup (256
+// consecutive sorted rows) visit only its window of sorted columns; a wave
+// also skips tiles outside its own window.
 
-__device__ __forceinline__ double pair_term(const double* uj, double ninv, const double (*tu)[kTile],
-                                            const double* tq, int c, const double* T, const double* ex)
+constexpr int kDimBlocks = 256;
+constexpr double kWindow = 37.7;
+
+__global__ __launch_bounds__(kBlock) void wdim_partial_kernel(WeightArgs a)
 {
-    double D = 0.0;
+    __shared__ double sh[kBlock];
+    const int M = (int)*a.M;
+    double s1[kNP], s2[kNP];
 #pragma unroll
-    for (int d = 0; d < kNP; ++d) {
-        const double df = uj[d] - tu[d][c];
-        D = __builtin_fma(df, df, D);
+    for (int d = 0; d < kNP; ++d) s1[d] = s2[d] = 0.0;
+    for (int k = blockIdx.x * kBlock + threadIdx.x; k < M; k += gridDim.x * kBlock) {
+#pragma unroll
+        for (int d = 0; d < kNP; ++d) {
+            const double v = a.cols[(size_t)k * 9 + d];
+            s1[d] += v;
+            s2[d] += v * v;
+        }
     }
-    const double arg = D * ninv;
-    return arg >= dm::kExpLo ? tq[c] * exp_tab(arg, T, ex) : 0.0;
+    for (int d = 0; d < kNP; ++d) {
+        const double t1 = block_sum_f64(s1[d], sh);
+        const double t2 = block_sum_f64(s2[d], sh);
+        if (threadIdx.x == 0) {
+            a.dimpart[blockIdx.x * 16 + d] = t1;
+            a.dimpart[blockIdx.x * 16 + 8 + d] = t2;
+        }
+    }
 }
 
+__global__ __launch_bounds__(kBlock) void wdim_pick_kernel(WeightArgs a)
+{
+    __shared__ double sh[kBlock];
+    const int M = (int)*a.M;
+    double best = -1.0;
+    int bd = 0;
+    for (int d = 0; d < kNP; ++d) {
+        const double t1 = block_sum_f64(threadIdx.x < kDimBlocks ? a.dimpart[threadIdx.x * 16 + d] : 0.0, sh);
+        const double t2 = block_sum_f64(threadIdx.x < kDimBlocks ? a.dimpart[threadIdx.x * 16 + 8 + d] : 0.0, sh);
+        const double mean = t1 / (double)M;
+        const double var = t2 / (double)M - mean * mean;
+        if (var > best) {
+            best = var;
+            bd = d;
+        }
+    }
+    if (threadIdx.x == 0) *a.dstar = bd;
+}
+
+__device__ __forceinline__ unsigned long long coord_key32(double u)
+{
+    const double c = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
+    return (unsigned long long)(unsigned int)(c * 4294967295.0);
+}
+
+__global__ __launch_bounds__(kBlock) void wcolkeys_kernel(WeightArgs a)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.npad) return;
+    const int M = (int)*a.M;
+    const int ds = *a.dstar;
+    a.colkeys[i] = i < (size_t)M ? (coord_key32(a.cols[i * 9 + ds]) << 32) | (unsigned long long)i : ~0ull;
+}
+
+__global__ __launch_bounds__(kBlock) void wcolgather_kernel(WeightArgs a)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const int M = (int)*a.M;
+    if (i >= (size_t)M) return;
+    const int ds = *a.dstar;
+    const size_t src = (size_t)(a.colkeys[i] & 0xFFFFFFFFull);
+    const double* c = a.cols + src * 9;
+    double* o = a.scols + i * 9;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) o[d] = c[d];
+    a.skey[i] = c[ds];
+}
+
+__global__ __launch_bounds__(kBlock) void wrowkeys_kernel(WeightArgs a)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.npad) return;
+    if (i >= (size_t)a.N) {
+        a.rowkeys[i] = ~0ull;
+        return;
+    }
+    const int ds = *a.dstar;
+    int e;
+    (void)__builtin_frexp(a.sigma[i], &e);
+    int oct = e + 40;
+    oct = oct < 0 ? 0 : (oct > 63 ? 63 : oct);
+    const unsigned long long hi = ((unsigned long long)oct << 26) | (coord_key32(a.u[i * kNP + ds]) >> 6);
+    a.rowkeys[i] = (hi << 32) | (unsigned long long)i;
+}
+
+// first index in sorted v[0..n) with v >= x (or > x when strict)
+__device__ __forceinline__ int lower_index(const double* v, int n, double x, bool strict)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (strict ? (v[mid] <= x) : (v[mid] < x)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off, kWave);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off, kWave);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Window of each row block (256 consecutive sorted rows): the sorted column
+// range that can hold a nonzero term for any of its rows.
+__global__ __launch_bounds__(kBlock) void wwindow_kernel(WeightArgs a)
+{
+    __shared__ double slo[kBlock / kWave], shi[kBlock / kWave];
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    const int ds = *a.dstar;
+    double lo = __builtin_inf(), hi = -__builtin_inf();
+    if (r < a.N) {
+        const size_t j = (size_t)(a.rowkeys[r] & 0xFFFFFFFFull);
+        const double R = kWindow * a.sigma[j];
+        const double x = a.u[j * kNP + ds];
+        lo = x - R;
+        hi = x + R;
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        slo[threadIdx.x / kWave] = lo;
+        shi[threadIdx.x / kWave] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < kBlock / kWave; ++q) {
+            lo = slo[q] < lo ? slo[q] : lo;
+            hi = shi[q] > hi ? shi[q] : hi;
+        }
+        lo = slo[0] < lo ? slo[0] : lo;
+        hi = shi[0] > hi ? shi[0] : hi;
+        const int M = (int)*a.M;
+        a.win[blockIdx.x] = make_int2(lower_index(a.skey, M, lo, false), lower_index(a.skey, M, hi, true));
+    }
+}
+
+// grid (row blocks, chunks): block (b, c) sums columns
+// [first_b + c CH, min(end_b, first_b + (c+1) CH)) for its 256 rows; chunks past
+// the window write zero partials and leave.
 __global__ __launch_bounds__(kBlock) void weights_kernel(WeightArgs a)
 {
     __shared__ double tu[kNP][kTile];
     __shared__ double tq[kTile];
     __shared__ double T[64];
-    if (threadIdx.x < 64) T[threadIdx.x] = dm::exp((double)threadIdx.x * 0.010830424696249145);  // 2^(i/64)
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    const bool active = j < a.N;
+    const int r = blockIdx.x * kBlock + threadIdx.x;   // sorted row position
+    const bool active = r < a.N;
+    const int2 wnd = a.win[blockIdx.x];
+    const int k0 = wnd.x + (int)blockIdx.y * a.cols_per_chunk;
+    const int k1 = min(wnd.y, k0 + a.cols_per_chunk);
+    if (k0 >= k1) {
+        if (active) a.partial[(size_t)blockIdx.y * a.N + r] = 0.0;
+        return;
+    }
+    if (threadIdx.x < 64) T[threadIdx.x] = wterm::table_entry(threadIdx.x);  // 2^(i/64)
+    const int ds = *a.dstar;
     double uj[kNP];
-    double ninv = 0.0;
+    double ninv = 0.0, lo = __builtin_inf(), hi = -__builtin_inf();
     if (active) {
+        const size_t j = (size_t)(a.rowkeys[r] & 0xFFFFFFFFull);
 #pragma unroll
-        for (int d = 0; d < kNP; ++d) uj[d] = a.u[(size_t)j * kNP + d];
+        for (int d = 0; d < kNP; ++d) uj[d] = a.u[j * kNP + d];
         const double sj = a.sigma[j];
         ninv = -1.0 / (2.0 * (sj * sj));
+        const double R = kWindow * sj;
+        lo = uj[ds] - R;
+        hi = uj[ds] + R;
     } else {
 #pragma unroll
         for (int d = 0; d < kNP; ++d) uj[d] = 0.0;
     }
-    const int M = (int)*a.M;
-    const int nt = (M + kTile - 1) / kTile;
-    const int S = a.chunks, c = blockIdx.y;
-    const int t0 = (int)(((long long)nt * c) / S), t1 = (int)(((long long)nt * (c + 1)) / S);
+    const double wlo = wave_min(lo), whi = wave_max(hi);
     double total = 0.0;
-    for (int tile = t0; tile < t1; ++tile) {
-        const int c0 = tile * kTile;
-        const int n = min(kTile, M - c0);
+    for (int c0 = k0; c0 < k1; c0 += kTile) {
+        const int n = min(kTile, k1 - c0);
         __syncthreads();
         if (threadIdx.x < n) {
-            const double* col = a.cols + (size_t)(c0 + threadIdx.x) * 9;
+            const double* col = a.scols + (size_t)(c0 + threadIdx.x) * 9;
 #pragma unroll
             for (int d = 0; d < kNP; ++d) tu[d][threadIdx.x] = col[d];
             tq[threadIdx.x] = col[8];
         }
         __syncthreads();
+        // this wave's rows cannot reach the tile: every term is exactly zero
+        if (a.skey[c0 + n - 1] < wlo || a.skey[c0] > whi) continue;
         double p0 = 0.0, p1 = 0.0;
         int cc = 0;
         for (; cc + 1 < n; cc += 2) {
@@ -307,15 +464,16 @@ __global__ __launch_bounds__(kBlock) void weights_kernel(WeightArgs a)
         if (cc < n) p0 += pair_term(uj, ninv, tu, tq, cc, T, a.ex);
         total += p0 + p1;
     }
-    if (active) a.partial[(size_t)c * a.N + j] = total;
+    if (active) a.partial[(size_t)blockIdx.y * a.N + r] = total;
 }
 
 __global__ __launch_bounds__(kBlock) void weights_finalize_kernel(WeightArgs a)
 {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= a.N) return;
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= a.N) return;
     double L = 0.0;
-    for (int c = 0; c < a.chunks; ++c) L += a.partial[(size_t)c * a.N + j];
+    for (int c = 0; c < a.chunks; ++c) L += a.partial[(size_t)c * a.N + r];
+    const size_t j = (size_t)(a.rowkeys[r] & 0xFFFFFFFFull);
     a.logw[j] = 8.0 * dm::log(a.sigma[j]) - dm::log(L);
 }
 
@@ -559,8 +717,31 @@ void launch_resample(const ResampleArgs& a, hipStream_t s)
 
 void launch_weights(const WeightArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(weights_kernel, dim3(blocks_of(a.N, kBlock), a.chunks), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(weights_finalize_kernel, dim3(blocks_of(a.N, kBlock)), dim3(kBlock), 0, s, a);
+    const dim3 b(kBlock);
+    const unsigned gp = blocks_of((int64_t)a.npad, kBlock);
+    hipLaunchKernelGGL(wdim_partial_kernel, dim3(kDimBlocks), b, 0, s, a);
+    hipLaunchKernelGGL(wdim_pick_kernel, dim3(1), b, 0, s, a);
+    hipLaunchKernelGGL(wcolkeys_kernel, dim3(gp), b, 0, s, a);
+    launch_sort_u64(a.colkeys, a.npad, s);
+    hipLaunchKernelGGL(wcolgather_kernel, dim3(blocks_of(a.N, kBlock)), b, 0, s, a);
+    hipLaunchKernelGGL(wrowkeys_kernel, dim3(gp), b, 0, s, a);
+    launch_sort_u64(a.rowkeys, a.npad, s);
+    hipLaunchKernelGGL(wwindow_kernel, dim3(blocks_of(a.N, kBlock)), b, 0, s, a);
+    hipLaunchKernelGGL(weights_kernel, dim3(blocks_of(a.N, kBlock), a.chunks), b, 0, s, a);
+    hipLaunchKernelGGL(weights_finalize_kernel, dim3(blocks_of(a.N, kBlock)), b, 0, s, a);
+}
+
+int weight_cols_per_chunk(int64_t N)
+{
+    int64_t ch = 2048;
+    while ((N + ch - 1) / ch > 32) ch <<= 1;
+    return (int)ch;
+}
+
+int weight_window_chunks(int64_t N)
+{
+    const int64_t ch = weight_cols_per_chunk(N);
+    return (int)((N + ch - 1) / ch);
 }
 
 void launch_normalise(const NormArgs& a, hipStream_t s)

@@ -1,0 +1,156 @@
+"""Batched mode: every run of a batch gives the same bits as the same run
+alone (single-run context, itself bit-exact against the oracle), under any
+schedule, with graph replays checked stage by stage against eager runs."""
+import numpy as np
+import pytest
+
+from paper_2106_15508_amd import abcsmc as A
+from paper_2106_15508_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _bits(x):
+    return np.ascontiguousarray(x, dtype=np.float64).view(np.uint64)
+
+
+def _runs():
+    base = W.tiny()
+    return [
+        base.with_(name="b0", n_particles=300, seed=3),
+        base.with_(name="b1", n_particles=1024, n_days=50, population=100_000, seed=4, obs_seed=11,
+                   step_schedule=W.STEP_FIXED, beta_a=2.0, beta_b=5),
+        base.with_(name="b2", n_particles=2048, n_days=40, population=1_000_000, seed=5, obs_seed=12),
+        base.with_(name="b3", n_particles=777, n_days=25, population=50_000, seed=6, obs_seed=13,
+                   sampler=W.SAMPLER_NORMAL_FLOOR),
+        base.with_(name="b4", n_particles=4096, n_days=60, population=3_000_000, seed=7, obs_seed=14),
+        base.with_(name="b5", n_particles=256, n_days=20, population=20_000, seed=8, obs_seed=15,
+                   step_is_variance=True),
+    ]
+
+
+def _plain(w, obs, stages, flags):
+    out = []
+    with A.Context(w, obs, flags=flags) as ctx:
+        for _ in range(stages):
+            info = ctx.round()
+            p = ctx.population()
+            _, d, wt = ctx.weights()
+            p["d"], p["W"], p["info"] = d, wt, info
+            out.append(p)
+    return out
+
+
+def _same(b, p, bi, pi_):
+    assert np.array_equal(b["index"], p["index"])
+    assert np.array_equal(_bits(b["u"]), _bits(p["u"]))
+    assert np.array_equal(_bits(b["d"]), _bits(p["d"]))
+    assert np.array_equal(_bits(b["sigma"]), _bits(p["sigma"]))
+    assert np.array_equal(b["parent"], p["parent"])
+    assert np.array_equal(b["attempts"], p["attempts"])
+    assert _bits([bi["eps_next"]])[0] == _bits([pi_["eps_next"]])[0]
+    assert bi["proposals"] == pi_["proposals"]
+    np.testing.assert_allclose(b["W"], p["W"], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("flags", [0, A.F_EARLY_EXIT])
+def test_batched_equals_plain(oracle, flags):
+    runs = _runs()
+    obs = [oracle.observations(w) for w in runs]
+    stages = 4
+    plain = [_plain(w, o, stages, flags) for w, o in zip(runs, obs)]
+    with A.Batch(runs, obs, flags=flags) as b:
+        for s in range(stages):
+            infos = b.round()
+            for r in range(len(runs)):
+                assert b.status(r) == A.OK
+                _same(b.population(r), plain[r][s], infos[r], plain[r][s]["info"])
+
+
+def test_schedules_give_identical_bits(oracle):
+    runs = _runs()
+    obs = [oracle.observations(w) for w in runs]
+    stages = 3
+    ref = None
+    scheds = [dict(propose_blocks=64, run_order=0, weight_cols=2048, issue_margin=1.05),
+              dict(propose_blocks=1024, run_order=2, weight_cols=8192, issue_margin=1.5),
+              dict()]
+    with A.Batch(runs, obs) as b:
+        for sc in scheds:
+            b.set_schedule(**sc)
+            b.reset()
+            b.run(stages)
+            pops = [b.population(r) for r in range(len(runs))]
+            if ref is None:
+                ref = pops
+                continue
+            for r in range(len(runs)):
+                for k in ("index", "parent", "attempts"):
+                    assert np.array_equal(pops[r][k], ref[r][k])
+                for k in ("u", "d", "sigma"):
+                    assert np.array_equal(_bits(pops[r][k]), _bits(ref[r][k]))
+                np.testing.assert_allclose(pops[r]["W"], ref[r]["W"], rtol=1e-12, atol=0)
+
+
+def test_replays_repeat(oracle):
+    runs = _runs()[:3]
+    obs = [oracle.observations(w) for w in runs]
+    with A.Batch(runs, obs) as b:
+        first = [b.round() for _ in range(3)]
+        pop1 = [b.population(r) for r in range(3)]
+        b.reset()
+        second = [b.round() for _ in range(3)]
+        pop2 = [b.population(r) for r in range(3)]
+    for s in range(3):
+        assert [i["eps_next"] for i in first[s]] == [i["eps_next"] for i in second[s]]
+    for r in range(3):
+        assert np.array_equal(_bits(pop1[r]["u"]), _bits(pop2[r]["u"]))
+        assert np.array_equal(_bits(pop1[r]["W"]), _bits(pop2[r]["W"]))
+
+
+def test_run_out_of_budget_stops_alone(oracle):
+    runs = _runs()[:3]
+    runs[1] = runs[1].with_(max_proposals=runs[1].n_particles)  # stage 0 fits, stage 1 cannot
+    obs = [oracle.observations(w) for w in runs]
+    alone = _plain(runs[2], obs[2], 3, 0)
+    with A.Batch(runs, obs) as b:
+        infos = b.run(3)
+        assert b.status(1) == A.EBUDGET
+        assert b.rounds_done(1) == 1
+        assert b.status(0) == A.OK and b.rounds_done(0) == 3
+        assert b.status(2) == A.OK and b.rounds_done(2) == 3
+        p = b.population(1)
+        assert np.all(p["W"] == 1.0 / runs[1].n_particles)   # still its stage-0 population
+        _same(b.population(2), alone[2], infos[2][2], alone[2]["info"])
+
+
+def test_autotune_and_cache(oracle, tmp_path):
+    runs = _runs()[:4]
+    obs = [oracle.observations(w) for w in runs]
+    cache = str(tmp_path / "sched.txt")
+    plain = [_plain(w, o, 3, 0) for w, o in zip(runs, obs)]
+    with A.Batch(runs, obs) as b:
+        s1 = b.autotune(stages=1, cache_path=cache)
+        assert b.rounds_done(0) == 0
+        s2 = b.autotune(stages=1, cache_path=cache)   # from the cache
+        assert s1 == s2
+        for s in range(3):
+            infos = b.round()
+            for r in range(len(runs)):
+                _same(b.population(r), plain[r][s], infos[r], plain[r][s]["info"])
+    assert open(cache).read().count("\n") == 1
+
+
+def test_uneven_batch_sampled_runs_match_plain(oracle):
+    runs = W.batched_runs(n_runs=24, seed=9, n_rounds=3)
+    obs = [oracle.observations(w) for w in runs]
+    with A.Batch(runs, obs, flags=A.F_EARLY_EXIT) as b:
+        b.run(3)
+        sizes = [w.n_particles * w.n_days for w in runs]
+        for r in (int(np.argmin(sizes)), int(np.argmax(sizes)), 5):
+            plain = _plain(runs[r], obs[r], 3, A.F_EARLY_EXIT)
+            p = b.population(r)
+            assert np.array_equal(p["index"], plain[2]["index"])
+            assert np.array_equal(_bits(p["u"]), _bits(plain[2]["u"]))
+            assert np.array_equal(_bits(p["d"]), _bits(plain[2]["d"]))
+            np.testing.assert_allclose(p["W"], plain[2]["W"], rtol=1e-12, atol=0)

@@ -115,6 +115,8 @@ typedef struct {
     int64_t n_k_propose;          /* proposal kernel launches (= batches) */
     int64_t sim_days;             /* proposal-days simulated (early exit stops counting) */
     int64_t weight_pairs;         /* N x survivors terms of the importance-weight sums */
+    int64_t weight_terms;         /* terms actually evaluated (the rest lie outside every window and
+                                     are exactly zero) */
 } abcsmc_round_info;
 
 typedef struct abcsmc_ctx abcsmc_ctx;

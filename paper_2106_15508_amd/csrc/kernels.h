@@ -32,6 +32,7 @@ struct StageCounters {
     unsigned long long survivors;  // previous particles with q > 0
     unsigned long long fallback;   // 1 if the prior set used d <= eps (no d < eps)
     unsigned long long days;       // proposal-days simulated over the batches run so far
+    unsigned long long terms;      // importance-weight terms evaluated (inside the windows)
 };
 
 // Population of one stage, array-of-structures for the per-particle gathers.
@@ -132,6 +133,7 @@ struct WeightArgs {
     size_t npad;            // padded sort length (power of two >= N)
     int2* win;              // per row block: sorted column range [first, end) of its window
     int32_t cols_per_chunk; // columns per grid-y chunk of a window
+    unsigned long long* terms;  // device counter of evaluated terms
     // exp by table: 64/ln2, ln2/64 (hi, lo), Taylor 1/2!, 1/3!, 1/4!, 1/5! (kernel
     // arguments so they sit in scalar registers)
     double ex[7];

@@ -480,6 +480,7 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
         wa.chunks = weight_window_chunks(N);
         wa.cols_per_chunk = weight_cols_per_chunk(N);
         wa.win = x->at<int2>(x->L.win);
+        wa.terms = &ctr->terms;
         wa.M = &ctr->survivors;
         wa.partial = x->at<double>(x->L.wpart);
         wa.logw = dst.logw;
@@ -505,7 +506,9 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
     HIPCHK(x, hipGetLastError());
     HIPCHK(x, hipEventRecord(x->ev[4], s));
     double hs[2] = {0, 0};
+    unsigned long long hterms = 0;
     HIPCHK(x, hipMemcpyAsync(hs, scal, sizeof hs, hipMemcpyDeviceToHost, s));
+    HIPCHK(x, hipMemcpyAsync(&hterms, &ctr->terms, sizeof hterms, hipMemcpyDeviceToHost, s));
     HIPCHK(x, hipStreamSynchronize(s));
 
     // commit the stage
@@ -538,6 +541,7 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
         I.n_k_propose = batches;
         I.sim_days = (int64_t)hc.days;
         I.weight_pairs = r == 0 ? 0 : (int64_t)N * (int64_t)hc.survivors;
+        I.weight_terms = (int64_t)hterms;
     }
     return ABCSMC_OK;
 }

@@ -13,8 +13,16 @@ namespace {
 // Proposal kernel of one batch: lane p makes proposal j = base + p and
 // publishes the wave's acceptance ballot for the ordered compaction.
 // ---------------------------------------------------------------------------
+// Waves per SIMD the register allocation aims for (the day loop is a chain of
+// long-latency FP64 divides, square roots and series; more resident waves
+// hide it, at the price of a few spilled registers).
+#ifndef ABCSMC_PROPOSE_WAVES
+#define ABCSMC_PROPOSE_WAVES 3
+#endif
+
 template <bool kRound0, int kSampler>
-__global__ __launch_bounds__(kBlock) void propose_kernel(ProposeArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ABCSMC_PROPOSE_WAVES)))
+void propose_kernel(ProposeArgs a)
 {
     const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
     const bool active = p < a.count;

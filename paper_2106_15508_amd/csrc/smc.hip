@@ -442,6 +442,8 @@ __global__ __launch_bounds__(kBlock) void weights_kernel(WeightArgs a)
         for (int d = 0; d < kNP; ++d) uj[d] = 0.0;
     }
     const double wlo = wave_min(lo), whi = wave_max(hi);
+    const unsigned long long lanes = (unsigned long long)__popcll(__ballot(active));
+    unsigned long long evaluated = 0;
     double total = 0.0;
     for (int c0 = k0; c0 < k1; c0 += kTile) {
         const int n = min(kTile, k1 - c0);
@@ -455,6 +457,7 @@ __global__ __launch_bounds__(kBlock) void weights_kernel(WeightArgs a)
         __syncthreads();
         // this wave's rows cannot reach the tile: every term is exactly zero
         if (a.skey[c0 + n - 1] < wlo || a.skey[c0] > whi) continue;
+        evaluated += lanes * (unsigned long long)n;
         double p0 = 0.0, p1 = 0.0;
         int cc = 0;
         for (; cc + 1 < n; cc += 2) {
@@ -465,6 +468,7 @@ __global__ __launch_bounds__(kBlock) void weights_kernel(WeightArgs a)
         total += p0 + p1;
     }
     if (active) a.partial[(size_t)blockIdx.y * a.N + r] = total;
+    if ((threadIdx.x & (kWave - 1)) == 0 && evaluated) atomicAdd(a.terms, evaluated);
 }
 
 __global__ __launch_bounds__(kBlock) void weights_finalize_kernel(WeightArgs a)

@@ -229,6 +229,95 @@ int abcsmc_batch_population(const abcsmc_batch* b, int32_t run, double* u, doubl
 void abcsmc_batch_free(abcsmc_batch* b); /* NULL-safe */
 const char* abcsmc_batch_last_error(const abcsmc_batch* b);
 
+/* ---------------------------------------------------------------------------
+ * Learned surrogate screen (an extension; the paper simulates every
+ * proposal).  A multilayer perceptron 8 -> 256 -> 256 -> 256 -> 3 with
+ * tanh-GELU activations maps a proposal's unit-cube coordinates (as 2u - 1)
+ * to y_c = log1p(sqrt(S_c)), where S_A, S_R, S_D are the per-series sums of
+ * squared differences whose total is the distance of §II-C; the score
+ * sum_c expm1(y_c)^2 predicts d^2.  Matrix products use bfloat16 operands
+ * (round to nearest even) on the matrix cores with FP32 accumulation; weights,
+ * gradients and Adam state (0.9, 0.999, 1e-8) are FP32.
+ *
+ * abcsmc_surrogate_enable fits the network on the GPU to n_train prior
+ * simulations (the stage-0 streams of indices 0 .. n_train-1; minibatches in
+ * index order).  In every later stage each batch of proposals is perturbed
+ * exactly as in the plain stage (same per-index streams), scored, and only
+ * proposals with score <= tau, or that pass an audit draw U < rho from their
+ * own AUDIT stream (purpose 4), are simulated; tau is the keep_frac
+ * percentile of the stage's first batch.  Acceptance is d <= eps on the exact
+ * FP64 simulation, first N in index order.  The stage's proposal density is
+ * q(u) (1{score <= tau} + rho 1{score > tau}) / Z, so an acceptance kept only
+ * by the audit gets log-weight - log rho.  The kept proposals of the first
+ * batch (up to tune_rows) are simulated in full and the network is trained
+ * on them for tune_epochs after the stage.  When a stage's audit estimate of
+ * the accepted mass with score > tau exceeds fn_max, later stages run plain.
+ * The state lives in its own device allocation (not the workspace);
+ * abcsmc_reset restores the network of the initial fit.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int64_t n_train;     /* prior simulations of the initial fit; 0 = 2^20; <= 2^24 */
+    int32_t epochs;      /* passes over them; 0 = 4; < 0: none (random network) */
+    int32_t batch;       /* minibatch rows; 0 = 1024; <= 16384 */
+    double lr;           /* Adam step; 0 = 1e-3 */
+    double keep_frac;    /* fraction of the first batch kept by score (sets tau); 0 = 0.1; in (0, 1] */
+    double audit_rho;    /* audit probability of a proposal with score > tau; 0 = 0.01; in (0, 1] */
+    int64_t pool;        /* proposals per batch at most; 0 = 2^22; in [1024, 2^22] */
+    int64_t tune_rows;   /* fine-tune rows per stage (rounded down to 256); 0 = min(65536, pool); < 0: none */
+    int32_t tune_epochs; /* fine-tune passes; 0 = 2; < 0: none */
+    double fn_max;       /* false-negative mass that ends screening; 0 = 0.05 */
+    uint64_t seed;       /* network initialisation: N(0, 1/fan_in) weights from the MLP stream (purpose 5) */
+} abcsmc_surrogate_config;
+
+typedef struct {
+    double loss_first;        /* mean squared error per output over the first epoch of the initial fit */
+    double loss_last;         /* ... and over its last epoch */
+    int64_t train_steps;      /* Adam steps so far */
+    double ms_train;          /* device time of the initial fit (data simulation + training) */
+    int32_t active;           /* 1 while stages are screened */
+    int32_t round;            /* last screened stage (-1: none yet) */
+    double tau;               /* its score threshold */
+    int64_t kept_screen;      /* proposals kept with score <= tau (over its whole batches) */
+    int64_t kept_audit;       /* proposals kept only by the audit */
+    int64_t accepted_screen;  /* acceptances among kept_screen */
+    int64_t accepted_audit;   /* acceptances among kept_audit */
+    double enrichment;        /* acceptance rate of kept_screen / estimated acceptance rate of all proposals */
+    double fn_mass;           /* audit estimate of the accepted mass with score > tau */
+    double ms_score;          /* device time of perturbation + network + keep decision in the stage */
+    double ms_tune;           /* device time of the fine-tune after the stage */
+} abcsmc_surrogate_info;
+
+/* Allocate, fit and switch on the screen for the following stages (scfg may
+ * be NULL: all defaults).  Replaces an earlier network. */
+int abcsmc_surrogate_enable(abcsmc_ctx* ctx, const abcsmc_surrogate_config* scfg);
+/* Free the surrogate state; later stages run plain.  NULL-safe surrogate. */
+int abcsmc_surrogate_disable(abcsmc_ctx* ctx);
+int abcsmc_surrogate_info_get(const abcsmc_ctx* ctx, abcsmc_surrogate_info* info);
+/* Current network, abcsmc_mlp_param_count() floats: W1[256][8] b1[256]
+ * W2[256][256] b2[256] W3[256][256] b3[256] W4[3][256] b4[3] (y = W h + b). */
+int abcsmc_surrogate_params(const abcsmc_ctx* ctx, float* params);
+/* First n rows of the initial fit's data: x n x 8, y n x 3 (either may be NULL). */
+int abcsmc_surrogate_data(const abcsmc_ctx* ctx, int64_t n, float* x, float* y);
+/* audit[j] = 1 if particle j of the last completed stage was accepted through
+ * the audit only (its log-weight carries - log rho), else 0. */
+int abcsmc_surrogate_audit(const abcsmc_ctx* ctx, uint8_t* audit);
+
+/* Network test hooks (host buffers, no context; each call allocates device memory). */
+int64_t abcsmc_mlp_param_count(void); /* 134659 */
+/* The initialisation of abcsmc_surrogate_enable for `seed`. */
+int abcsmc_mlp_init(uint64_t seed, float* params);
+/* out n x 3 = network(x n x 8); 1 <= n <= 65536. */
+int abcsmc_mlp_forward(const float* params, int64_t n, const float* x, float* out);
+/* Gradient of the loss mean over n x 3 of (out - y)^2 with respect to the
+ * parameters (same layout), and the loss; 1 <= n <= 16384. */
+int abcsmc_mlp_gradients(const float* params, int64_t n, const float* x, const float* y, float* grad,
+                         double* loss);
+/* epochs passes of minibatch Adam (fresh state) over (x, y) in row order,
+ * updating params in place; losses: epochs entries (mean squared error per
+ * output over each pass, before each step's update) or NULL. */
+int abcsmc_mlp_train(float* params, int64_t n, const float* x, const float* y, int32_t batch, int32_t epochs,
+                     double lr, double* losses);
+
 void abcsmc_free(abcsmc_ctx* ctx); /* NULL-safe */
 const char* abcsmc_strerror(int code);
 const char* abcsmc_last_error(const abcsmc_ctx* ctx); /* NULL ctx: last error of a context-less call */

@@ -34,6 +34,9 @@ EXPORTS = (
     "abcsmc_batch_get_schedule", "abcsmc_batch_autotune", "abcsmc_batch_round", "abcsmc_batch_run",
     "abcsmc_batch_reset", "abcsmc_batch_status", "abcsmc_batch_rounds_done", "abcsmc_batch_population",
     "abcsmc_batch_free", "abcsmc_batch_last_error",
+    "abcsmc_surrogate_enable", "abcsmc_surrogate_disable", "abcsmc_surrogate_info_get", "abcsmc_surrogate_params",
+    "abcsmc_surrogate_data", "abcsmc_surrogate_audit", "abcsmc_mlp_param_count", "abcsmc_mlp_init",
+    "abcsmc_mlp_forward", "abcsmc_mlp_gradients", "abcsmc_mlp_train",
 )
 
 
@@ -74,6 +77,27 @@ class RoundInfo(C.Structure):
         ("ms_total", C.c_double), ("ms_k_propose", C.c_double), ("ms_k_weights", C.c_double),
         ("n_k_propose", C.c_int64), ("sim_days", C.c_int64), ("weight_pairs", C.c_int64),
         ("weight_terms", C.c_int64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SurrogateConfig(C.Structure):
+    _fields_ = [
+        ("n_train", C.c_int64), ("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double),
+        ("keep_frac", C.c_double), ("audit_rho", C.c_double), ("pool", C.c_int64), ("tune_rows", C.c_int64),
+        ("tune_epochs", C.c_int32), ("fn_max", C.c_double), ("seed", C.c_uint64),
+    ]
+
+
+class SurrogateInfo(C.Structure):
+    _fields_ = [
+        ("loss_first", C.c_double), ("loss_last", C.c_double), ("train_steps", C.c_int64),
+        ("ms_train", C.c_double), ("active", C.c_int32), ("round", C.c_int32), ("tau", C.c_double),
+        ("kept_screen", C.c_int64), ("kept_audit", C.c_int64), ("accepted_screen", C.c_int64),
+        ("accepted_audit", C.c_int64), ("enrichment", C.c_double), ("fn_mass", C.c_double),
+        ("ms_score", C.c_double), ("ms_tune", C.c_double),
     ]
 
     def as_dict(self):
@@ -129,6 +153,17 @@ def load(path: Optional[str] = None):
         "abcsmc_batch_population": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
         "abcsmc_batch_free": (None, [vp]),
         "abcsmc_batch_last_error": (C.c_char_p, [vp]),
+        "abcsmc_surrogate_enable": (C.c_int, [vp, vp]),
+        "abcsmc_surrogate_disable": (C.c_int, [vp]),
+        "abcsmc_surrogate_info_get": (C.c_int, [vp, vp]),
+        "abcsmc_surrogate_params": (C.c_int, [vp, vp]),
+        "abcsmc_surrogate_data": (C.c_int, [vp, i64, vp, vp]),
+        "abcsmc_surrogate_audit": (C.c_int, [vp, vp]),
+        "abcsmc_mlp_param_count": (i64, []),
+        "abcsmc_mlp_init": (C.c_int, [u64, vp]),
+        "abcsmc_mlp_forward": (C.c_int, [vp, i64, vp, vp]),
+        "abcsmc_mlp_gradients": (C.c_int, [vp, i64, vp, vp, vp, vp]),
+        "abcsmc_mlp_train": (C.c_int, [vp, i64, vp, vp, i32, i32, d, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -265,6 +300,37 @@ class Context:
         _check(self.L.abcsmc_resampling(self._h, _p(q), _p(cdf)), self._h)
         return q, cdf
 
+    # -- learned surrogate screen
+    def surrogate_enable(self, **kw) -> dict:
+        """abcsmc_surrogate_enable with SurrogateConfig fields as keywords
+        (unset = library default); returns the surrogate info."""
+        sc = SurrogateConfig(**kw)
+        _check(self.L.abcsmc_surrogate_enable(self._h, C.byref(sc)), self._h)
+        return self.surrogate_info()
+
+    def surrogate_disable(self):
+        _check(self.L.abcsmc_surrogate_disable(self._h), self._h)
+
+    def surrogate_info(self) -> dict:
+        i = SurrogateInfo()
+        _check(self.L.abcsmc_surrogate_info_get(self._h, C.byref(i)), self._h)
+        return i.as_dict()
+
+    def surrogate_params(self) -> np.ndarray:
+        p = np.zeros(mlp_param_count(), np.float32)
+        _check(self.L.abcsmc_surrogate_params(self._h, _p(p)), self._h)
+        return p
+
+    def surrogate_data(self, n: int):
+        x, y = np.zeros((n, 8), np.float32), np.zeros((n, 3), np.float32)
+        _check(self.L.abcsmc_surrogate_data(self._h, n, _p(x), _p(y)), self._h)
+        return x, y
+
+    def surrogate_audit(self) -> np.ndarray:
+        a = np.zeros(self.N, np.uint8)
+        _check(self.L.abcsmc_surrogate_audit(self._h, _p(a)), self._h)
+        return a
+
     def close(self):
         if self._h:
             self.L.abcsmc_free(self._h)
@@ -281,6 +347,47 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+# -- network hooks (host arrays in, host arrays out)
+def mlp_param_count() -> int:
+    return int(load().abcsmc_mlp_param_count())
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    p = np.zeros(mlp_param_count(), np.float32)
+    _check(load().abcsmc_mlp_init(seed, _p(p)))
+    return p
+
+
+def _f32(a, shape=None) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def mlp_forward(params, x) -> np.ndarray:
+    params, x = _f32(params), _f32(x)
+    n = x.shape[0]
+    out = np.zeros((n, 3), np.float32)
+    _check(load().abcsmc_mlp_forward(_p(params), n, _p(x), _p(out)))
+    return out
+
+
+def mlp_gradients(params, x, y):
+    params, x, y = _f32(params), _f32(x), _f32(y)
+    g = np.zeros_like(params)
+    loss = C.c_double()
+    _check(load().abcsmc_mlp_gradients(_p(params), x.shape[0], _p(x), _p(y), _p(g), C.byref(loss)))
+    return g, loss.value
+
+
+def mlp_train(params, x, y, batch: int, epochs: int, lr: float):
+    p, x, y = _f32(params).copy(), _f32(x), _f32(y)
+    losses = np.zeros(max(epochs, 1))
+    _check(load().abcsmc_mlp_train(_p(p), x.shape[0], _p(x), _p(y), batch, epochs, lr, _p(losses)))
+    return p, losses[:epochs]
 
 
 def run(w: W.Workload, obs, n_rounds: Optional[int] = None, **over):

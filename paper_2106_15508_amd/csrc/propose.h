@@ -21,11 +21,14 @@ namespace lane {
 // distance would exceed eps).  Draw k of day t is word k of the stream
 // (index, round, SIM, t): blocks 0, 0, 1, 1, 2.
 // ---------------------------------------------------------------------------
-template <int kSampler, bool kTraj>
+// With kSplit the three series' sums of squares also go to split[0..2]
+// (no early exit; the surrogate's training targets); the returned distance
+// is the same as without.
+template <int kSampler, bool kTraj, bool kSplit = false>
 __device__ __forceinline__ double simulate_distance(const Model& m, const double* th,
                                                     const double* __restrict__ obs, uint32_t round,
                                                     uint32_t index, double exit_thr, int64_t* traj,
-                                                    int32_t& days)
+                                                    int32_t& days, double* split = nullptr)
 {
     const double alpha0 = th[0], alpha_c = th[1], n_exp = th[2], beta = th[3];
     const double gamma = th[4], delta = th[5], eta = th[6], kappa = th[7];
@@ -84,7 +87,18 @@ __device__ __forceinline__ double simulate_distance(const Model& m, const double
             row[0] = (int64_t)S; row[1] = (int64_t)I; row[2] = (int64_t)A;
             row[3] = (int64_t)R; row[4] = (int64_t)D; row[5] = (int64_t)Ru;
         }
-        if (!kTraj) {
+        if (kSplit) {
+            const double* o = obs + (size_t)(t + 1) * 3;
+            const double dA = A - o[0];
+            const double dR = R - o[1];
+            const double dD = D - o[2];
+            split[0] = split[0] + dA * dA;
+            split[1] = split[1] + dR * dR;
+            split[2] = split[2] + dD * dD;
+            acc = acc + dA * dA;
+            acc = acc + dR * dR;
+            acc = acc + dD * dD;
+        } else if (!kTraj) {
             const double* o = obs + (size_t)(t + 1) * 3;
             const double dA = A - o[0];
             const double dR = R - o[1];
@@ -155,8 +169,10 @@ struct ProposalOut {
 // the Box-Muller pairs of words 1..4; u = u_k + sigma z (eq. 17); stop at the
 // first u inside [0,1]^8.  Then simulate, distance, accept iff d <= eps.
 // ---------------------------------------------------------------------------
-template <bool kRound0, int kSampler>
-__device__ __forceinline__ void propose_one(const Model& m, const ProposalIn& a, uint32_t j, ProposalOut& o)
+// Stage-0 prior draw (kRound0) or the perturbation attempts of stage >= 1:
+// fills o.u, o.sigma, o.parent, o.att and o.valid.
+template <bool kRound0>
+__device__ __forceinline__ void perturb_one(const Model& m, const ProposalIn& a, uint32_t j, ProposalOut& o)
 {
     double* u = o.u;
     double sigma = 0.0;
@@ -224,21 +240,27 @@ __device__ __forceinline__ void propose_one(const Model& m, const ProposalIn& a,
             if (!valid) att = -a.max_attempts;
         }
     }
-    double d = __builtin_inf();
-    bool acc = false;
-    int32_t days = 0;
-    if (valid) {
-        double th[kNP];
-#pragma unroll
-        for (int q = 0; q < kNP; ++q) th[q] = m.lo[q] + u[q] * m.width[q];
-        d = simulate_distance<kSampler, false>(m, th, a.obs, a.round, j, a.exit_thr, nullptr, days);
-        acc = d <= a.eps;
-    }
     o.sigma = sigma;
     o.parent = parent;
     o.att = att;
-    o.d = d;
     o.valid = valid;
+}
+
+template <bool kRound0, int kSampler>
+__device__ __forceinline__ void propose_one(const Model& m, const ProposalIn& a, uint32_t j, ProposalOut& o)
+{
+    perturb_one<kRound0>(m, a, j, o);
+    double d = __builtin_inf();
+    bool acc = false;
+    int32_t days = 0;
+    if (o.valid) {
+        double th[kNP];
+#pragma unroll
+        for (int q = 0; q < kNP; ++q) th[q] = m.lo[q] + o.u[q] * m.width[q];
+        d = simulate_distance<kSampler, false>(m, th, a.obs, a.round, j, a.exit_thr, nullptr, days);
+        acc = d <= a.eps;
+    }
+    o.d = d;
     o.acc = acc;
     o.days = days;
 }

@@ -13,30 +13,12 @@
 
 #include "abcsmc.h"
 #include "kernels.h"
+#include "ctx.h"
 
 using namespace abcsmc;
+using namespace abcsmc::rt;
 
 namespace {
-
-thread_local std::string g_last_error;
-
-struct DevPop {
-    double* u;
-    double* d;
-    double* sigma;
-    int32_t* parent;
-    uint32_t* index;
-    int32_t* att;
-    double* logw;
-    double* W;
-    Population view() const { return Population{u, d, sigma, parent, index, att, logw, W}; }
-};
-
-// Byte layout of the device workspace (every region 256-byte aligned).
-struct Layout {
-    size_t obs, pop[2][8], q, cdf, cols, st_u, st_d, st_sigma, st_parent, st_att, wave_mask, wave_off,
-        ctr, scal, theta, red[5], hist, sel, wpart, rowkeys, colkeys, scols, skey, dimpart, dstar, win, total;
-};
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -106,13 +88,6 @@ Layout make_layout(const abcsmc_config& c)
     return L;
 }
 
-int fail(std::string* where, int code, const std::string& msg)
-{
-    if (where) *where = msg;
-    g_last_error = msg;
-    return code;
-}
-
 int validate(const abcsmc_config* c, const int64_t* obs, std::string* err)
 {
     if (!c) return fail(err, ABCSMC_EINVAL, "config is NULL");
@@ -165,45 +140,6 @@ Model make_model(const abcsmc_config& c, const int64_t* obs0)
 
 }  // namespace
 
-#define HIPCHK(ctx, expr)                                                                  \
-    do {                                                                                   \
-        hipError_t e_ = (expr);                                                            \
-        if (e_ != hipSuccess) {                                                            \
-            (ctx)->broken = true;                                                          \
-            return fail(&(ctx)->err, ABCSMC_EDEVICE,                                       \
-                        std::string(#expr) + ": " + hipGetErrorString(e_));                \
-        }                                                                                  \
-    } while (0)
-
-struct abcsmc_ctx {
-    abcsmc_config cfg{};
-    Model model{};
-    Layout L{};
-    std::vector<int64_t> obs;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    char* ws = nullptr;
-    bool own_ws = false;
-    bool broken = false;
-    std::string err;
-    hipEvent_t ev[9] = {};
-    DevPop pop[2]{};
-    int cur = 0;                 // pop[cur] holds the last completed stage
-    int32_t rounds = 0;          // stages completed
-    double eps_next = INFINITY;  // eps of the next stage
-    double eps1 = INFINITY;      // eps of stage 1 (eq. 16 normaliser)
-    double last_rate = 0.5;      // acceptance rate of the last stage (batch sizing)
-    int64_t N = 0;
-    template <typename T>
-    T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
-    Scratch scratch() const
-    {
-        return Scratch{at<unsigned long long>(L.red[0]), at<unsigned long long>(L.red[1]),
-                       at<unsigned long long>(L.red[2]), at<double>(L.red[3]), at<double>(L.red[4]),
-                       at<unsigned int>(L.hist), at<unsigned long long>(L.sel)};
-    }
-};
-
 namespace {
 
 void bind_pops(abcsmc_ctx* x)
@@ -218,13 +154,6 @@ void bind_pops(abcsmc_ctx* x)
         x->pop[p].logw = x->at<double>(x->L.pop[p][6]);
         x->pop[p].W = x->at<double>(x->L.pop[p][7]);
     }
-}
-
-float elapsed(hipEvent_t a, hipEvent_t b)
-{
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
-    return ms;
 }
 
 }  // namespace
@@ -266,6 +195,7 @@ void abcsmc_free(abcsmc_ctx* ctx)
 {
     if (!ctx) return;
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    surrogate_free(ctx->sur);
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
@@ -353,6 +283,7 @@ int abcsmc_reset(abcsmc_ctx* x)
     x->eps_next = INFINITY;
     x->eps1 = INFINITY;
     x->last_rate = 0.5;
+    if (x->sur) return surrogate_reset(x);
     return ABCSMC_OK;
 }
 
@@ -388,7 +319,12 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
                                 ? (eps * eps) * (1.0 + 0x1p-48)
                                 : INFINITY;
 
+    const bool screened = surrogate_screens(x, r);
     HIPCHK(x, hipMemsetAsync(ctr, 0, sizeof(StageCounters), s));
+    if (x->sur) {
+        const int rc = surrogate_stage_begin(x, nxt);
+        if (rc) return rc;
+    }
     HIPCHK(x, hipEventRecord(x->ev[0], s));
     if (r > 0) {
         ResampleArgs ra{prev.d, prev.u, N, eps, x->at<uint64_t>(x->L.q), x->at<uint64_t>(x->L.cdf),
@@ -434,7 +370,11 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
     int64_t base = 0, batches = 0;
     double ms_k_propose = 0.0;
     StageCounters hc{};
-    for (;;) {
+    if (screened) {
+        const int rc = surrogate_batches(x, pa, dst, nxt, hc, base, batches, ms_k_propose);
+        if (rc) return rc;
+    }
+    while (!screened) {
         int64_t B;
         if (r == 0) {
             B = std::min<int64_t>(cap, (int64_t)N - (int64_t)hc.accepted);
@@ -496,6 +436,10 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
         launch_weights(wa, s);
         HIPCHK(x, hipGetLastError());
         HIPCHK(x, hipEventRecord(x->ev[8], s));
+        if (screened) {
+            const int rc = surrogate_weights(x, dst, nxt);
+            if (rc) return rc;
+        }
         NormArgs na{dst.logw, dst.W, N, x->scratch(), scal + 1};
         launch_normalise(na, s);
     }
@@ -516,6 +460,10 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
     x->rounds = r + 1;
     if (r == 1) x->eps1 = eps;
     x->eps_next = hs[0];
+    if (screened) {
+        const int rc = surrogate_stage_end(x, r);
+        if (rc) return rc;
+    }
     if (info) {
         abcsmc_round_info& I = *info;
         std::memset(&I, 0, sizeof I);

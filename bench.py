@@ -31,6 +31,7 @@ if ROOT not in sys.path:
 
 # MI355X published peaks
 PEAK_FP64_TFLOPS = 78.6
+PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
 # FP64 flops (fma = 2) of one importance-weight term: 8 differences, 8 fma
@@ -46,8 +47,8 @@ FLOPS_PER_PAIR = 8 + 16 + 1 + 18 + 1 + 1
 TRAFFIC_SOURCES = ("paper_2106_15508_amd/csrc/smc.hip", "paper_2106_15508_amd/csrc/dmath.h",
                    "paper_2106_15508_amd/csrc/kernels.h")
 TRAFFIC_MEASURED = {
-    # weights_kernel, c2: FETCH_SIZE 23073 KiB x 2 + WRITE_SIZE 4096 KiB x 1 per launch
-    ("227281976887633a", "c2", "weights_kernel"): 23073 * 1024 * 2 + 4096 * 1024,
+    # weights_kernel (windowed), c2: FETCH_SIZE 116340 KiB x 2 + WRITE_SIZE 33355 KiB x 1 per launch
+    ("063017602bdcc342", "c2", "weights_kernel"): 116340 * 1024 * 2 + 33355 * 1024,
 }
 # FP64 flops of one simulated proposal-day with all five transitions in the
 # normal branch of the binomial draw: state sums 2, g (log 34, exp 33, 4) 71,
@@ -61,7 +62,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
                     help="c4: 96 uneven runs in the batched mode, compared with the same runs one at a time")
     ap.add_argument("--runs", type=int, default=96, help="c4: number of runs")
     ap.add_argument("--early-exit", type=int, default=1, help="stop simulating a proposal once its "
@@ -187,6 +188,98 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_surrogate(args):
+    """The headline workload with the learned screen: per step, stage 0, the
+    network's initial fit on 2^22 prior simulations (2 passes, minibatch
+    8192, included in the step), then nine screened stages (keep 10% of each
+    stage's first batch by score, audit rho = 1%, screening kept on in every
+    stage).  The same steps of the plain form run beside it for the
+    comparison of throughput and posterior moments."""
+    import numpy as np
+    import torch
+
+    from paper_2106_15508_amd import abcsmc as A
+    from paper_2106_15508_amd import workloads as W
+
+    w = W.C2
+    R = w.n_rounds
+    obs = A.observations(w)
+    stream = torch.cuda.current_stream()
+    flags = A.F_EARLY_EXIT if args.early_exit else 0
+    sur = dict(n_train=1 << 22, epochs=2, batch=8192, keep_frac=0.1, audit_rho=0.01, fn_max=1.0, seed=11)
+
+    def one(ctx, screened):
+        ctx.reset()
+        infos = [ctx.round()]
+        if screened:
+            ctx.surrogate_enable(**sur)
+        sinfo = []
+        for _ in range(R - 1):
+            infos.append(ctx.round())
+            if screened:
+                sinfo.append(ctx.surrogate_info())
+        return infos, sinfo
+
+    def moments(ctx):
+        th, _, wt = ctx.weights()
+        mu = (wt[:, None] * th).sum(0)
+        var = (wt[:, None] * (th - mu) ** 2).sum(0)
+        return mu, var
+
+    res = {}
+    for screened in (False, True):
+        ctx = A.Context(w, obs, stream=stream.cuda_stream, flags=flags)
+        for _ in range(args.warmup):
+            one(ctx, screened)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        runs = [one(ctx, screened) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / args.steps
+        mu, var = moments(ctx)
+        res[screened] = dict(sec=sec, runs=runs, mu=mu, var=var, sinfo=None if not screened else ctx.surrogate_info())
+        ctx.close()
+    N = w.n_particles
+    plain, scr = res[False], res[True]
+    last_i, last_s = scr["runs"][-1]
+    si0 = scr["sinfo"]
+    train_flops = si0["train_flops"]
+    ms_train = si0["ms_train"]
+    achieved = train_flops / (ms_train * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_BF16_TFLOPS, 5), "traffic": None,
+                "kernel": "network initial fit (gemm_bf16_kernel and its epilogue kernels)",
+                "avg_launch_ms": None, "phase_ms": round(ms_train, 3), "flops": train_flops}
+    rel_mu = np.abs(scr["mu"] - plain["mu"]) / np.maximum(np.abs(plain["mu"]), 1e-300)
+    out = {
+        "metric": "accepted particles/s", "value": N * R / scr["sec"], "unit": "accepted particles/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": scr["sec"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+bf16",
+        "data": "synthetic",
+        "config": {"workload": f"C5: C2 (P={w.population}, T={w.n_days}, N={N}, stages={R}) with the learned "
+                               "screen: fit on 2^22 prior simulations x 2 passes, keep 10%, audit 1%",
+                   "early_exit": bool(args.early_exit)},
+        "plain_value": N * R / plain["sec"],
+        "speedup_vs_plain": plain["sec"] / scr["sec"],
+        "surrogate": {
+            "ms_data": si0["ms_data"], "ms_train": si0["ms_train"], "loss_first": si0["loss_first"],
+            "loss_last": si0["loss_last"],
+            "enrichment": [round(s["enrichment"], 3) for s in last_s],
+            "fn_mass": [round(s["fn_mass"], 4) for s in last_s],
+            "ms_score": [round(s["ms_score"], 2) for s in last_s],
+            "ms_tune": [round(s["ms_tune"], 2) for s in last_s],
+            "proposals": [i["proposals"] for i in last_i[1:]],
+            "plain_proposals": [i["proposals"] for i in plain["runs"][-1][0][1:]],
+        },
+        "posterior": {"mean_rel_diff_vs_plain": [round(float(v), 4) for v in rel_mu],
+                      "ess_final": [round(plain["runs"][-1][0][-1]["ess"], 1), round(last_i[-1]["ess"], 1)],
+                      "note": "different stage sequences (the screen changes which proposals survive); the "
+                              "comparison is meaningful only where both final ESS are large"},
+        "roofline": roofline,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -202,6 +295,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "c4":
         return bench_batched(args)
+    if args.workload == "c5":
+        return bench_surrogate(args)
     if args.calibrate_copy:
         src = torch.ones(args.calibrate_copy, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

@@ -258,7 +258,7 @@ const char* abcsmc_batch_last_error(const abcsmc_batch* b);
 typedef struct {
     int64_t n_train;     /* prior simulations of the initial fit; 0 = 2^20; <= 2^24 */
     int32_t epochs;      /* passes over them; 0 = 4; < 0: none (random network) */
-    int32_t batch;       /* minibatch rows; 0 = 1024; <= 16384 */
+    int32_t batch;       /* minibatch rows; 0 = 8192; <= 16384 */
     double lr;           /* Adam step; 0 = 1e-3 */
     double keep_frac;    /* fraction of the first batch kept by score (sets tau); 0 = 0.1; in (0, 1] */
     double audit_rho;    /* audit probability of a proposal with score > tau; 0 = 0.01; in (0, 1] */
@@ -273,7 +273,7 @@ typedef struct {
     double loss_first;        /* mean squared error per output over the first epoch of the initial fit */
     double loss_last;         /* ... and over its last epoch */
     int64_t train_steps;      /* Adam steps so far */
-    double ms_train;          /* device time of the initial fit (data simulation + training) */
+    double ms_train;          /* device time of the initial fit's training steps */
     int32_t active;           /* 1 while stages are screened */
     int32_t round;            /* last screened stage (-1: none yet) */
     double tau;               /* its score threshold */
@@ -285,6 +285,9 @@ typedef struct {
     double fn_mass;           /* audit estimate of the accepted mass with score > tau */
     double ms_score;          /* device time of perturbation + network + keep decision in the stage */
     double ms_tune;           /* device time of the fine-tune after the stage */
+    double ms_data;           /* device time of the initial fit's data simulation (ms_train: its training) */
+    int64_t train_flops;      /* matrix-product flops of the initial fit (2 per multiply-add, 3 products per
+                                 layer and sample: forward, data gradient, weight gradient) */
 } abcsmc_surrogate_info;
 
 /* Allocate, fit and switch on the screen for the following stages (scfg may

@@ -97,7 +97,7 @@ class SurrogateInfo(C.Structure):
         ("ms_train", C.c_double), ("active", C.c_int32), ("round", C.c_int32), ("tau", C.c_double),
         ("kept_screen", C.c_int64), ("kept_audit", C.c_int64), ("accepted_screen", C.c_int64),
         ("accepted_audit", C.c_int64), ("enrichment", C.c_double), ("fn_mass", C.c_double),
-        ("ms_score", C.c_double), ("ms_tune", C.c_double),
+        ("ms_score", C.c_double), ("ms_tune", C.c_double), ("ms_data", C.c_double), ("train_flops", C.c_int64),
     ]
 
     def as_dict(self):

@@ -30,14 +30,20 @@ struct MlpView {
     float *W1, *b1, *W2, *b2, *W3, *b3, *W4, *b4;
 };
 
-// Activation scratch for up to `rows` samples.
+// Split-K slices of the weight-gradient products (and the bias-gradient
+// partial sums): at most kSplitMax slices of up to 256 x 256.
+constexpr int kSplitMax = 32;
+constexpr int64_t kSplitFloats = (int64_t)kSplitMax * kH * kH;
+
+// Activation scratch for up to `rows` samples, plus kSplitFloats of `part`.
 struct MlpActs {
-    float *a1, *a2, *a3, *h1, *h2, *h3, *out, *d1, *d2, *d3;
+    float *a1, *a2, *a3, *h1, *h2, *h3, *out, *d1, *d2, *d3, *part;
 };
 
 MlpView mlp_view(float* params);
-void launch_gemm(const GemmArgs& g, hipStream_t s);
-void launch_colsum(const float* X, int M, int N, int ld, float* out, hipStream_t s);
+// part: split-K scratch (kSplitFloats) or null (no split).
+void launch_gemm(const GemmArgs& g, float* part, hipStream_t s);
+void launch_colsum(const float* X, int M, int N, int ld, float* out, float* part, hipStream_t s);
 void launch_mse_grad(const float* out, const float* y, int n, float* dout, float* se, hipStream_t s);
 void launch_adam(float* w, const float* g, float* m, float* v, int n, float lr, int step, hipStream_t s);
 void launch_score(const float* out, int n, double* score, hipStream_t s);

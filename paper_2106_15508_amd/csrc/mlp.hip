@@ -6,6 +6,8 @@
 // master weights, activations, gradients and Adam state are FP32.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 #include "mlp.h"
 
@@ -16,74 +18,147 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTM = 64, kTN = 64, kTK = 32;  // workgroup tile (M, N) and K step
+constexpr int kTK = 32;           // K step (one v_mfma_f32_16x16x32_bf16)
+constexpr int kLdsK = kTK + 8;    // LDS row pitch in bf16 (16-byte skew between rows)
 
 __device__ __forceinline__ __bf16 to_bf16(float f) { return (__bf16)f; }  // round to nearest even
+
+// tanh(y) = 1 - 2 / (1 + e^{2y}) with the hardware exp and divide (absolute
+// error ~1e-7, saturates correctly at +-inf).
+__device__ __forceinline__ float tanh_fast(float y) { return 1.0f - __fdividef(2.0f, 1.0f + __expf(2.0f * y)); }
 
 // GELU, tanh form: 0.5 x (1 + tanh(c (x + 0.044715 x^3))), c = sqrt(2/pi)
 __device__ __forceinline__ float gelu_f(float x)
 {
     const float c = 0.7978845608028654f;
-    const float t = tanhf(c * (x + 0.044715f * x * x * x));
+    const float t = tanh_fast(c * (x + 0.044715f * x * x * x));
     return 0.5f * x * (1.0f + t);
 }
 __device__ __forceinline__ float gelu_grad_f(float x)
 {
     const float c = 0.7978845608028654f;
     const float x2 = x * x;
-    const float t = tanhf(c * (x + 0.044715f * x2 * x));
+    const float t = tanh_fast(c * (x + 0.044715f * x2 * x));
     return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * c * (1.0f + 3.0f * 0.044715f * x2);
+}
+
+// Stage rows [r0, r0 + kR) x k [k0, k0 + 32) of op(X) into S[row][k] as bf16,
+// op(X)(r, k) = kcontig ? X[r*ld + k] : X[k*ld + r]; entries outside R x K are 0.
+// vec: ld % 4 == 0 and X 16-byte aligned (float4 loads along the contiguous axis).
+template <int kR>
+__device__ __forceinline__ void stage_tile(const float* __restrict__ X, int ld, bool kcontig, int R, int K, int r0,
+                                           int k0, __bf16 (*S)[kLdsK], int t, bool vec)
+{
+    constexpr int kIters = kR * kTK / 4 / 256;  // float4 per thread
+    if (kcontig) {
+#pragma unroll
+        for (int i = 0; i < kIters; ++i) {
+            const int idx = t + 256 * i;
+            const int r = idx >> 3, kk = (idx & 7) * 4;
+            const int gr = r0 + r, gk = k0 + kk;
+            float v[4] = {0.f, 0.f, 0.f, 0.f};
+            if (gr < R) {
+                const float* src = X + (size_t)gr * ld + gk;
+                if (vec && gk + 3 < K) {
+                    const float4 f = *reinterpret_cast<const float4*>(src);
+                    v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
+                } else {
+                    for (int e = 0; e < 4; ++e)
+                        if (gk + e < K) v[e] = src[e];
+                }
+            }
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            const bf16x4 pk = {to_bf16(v[0]), to_bf16(v[1]), to_bf16(v[2]), to_bf16(v[3])};
+            *reinterpret_cast<bf16x4*>(&S[r][kk]) = pk;  // 8-byte aligned: kk % 4 == 0, pitch 80 bytes
+        }
+    } else {
+        constexpr int kRow4 = kR / 4;  // float4 per k row
+#pragma unroll
+        for (int i = 0; i < kIters; ++i) {
+            const int idx = t + 256 * i;
+            const int kk = idx / kRow4, r = (idx % kRow4) * 4;
+            const int gk = k0 + kk, gr = r0 + r;
+            float v[4] = {0.f, 0.f, 0.f, 0.f};
+            if (gk < K) {
+                const float* src = X + (size_t)gk * ld + gr;
+                if (vec && gr + 3 < R) {
+                    const float4 f = *reinterpret_cast<const float4*>(src);
+                    v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
+                } else {
+                    for (int e = 0; e < 4; ++e)
+                        if (gr + e < R) v[e] = src[e];
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) S[r + e][kk] = to_bf16(v[e]);
+        }
+    }
 }
 
 // C[M x N] = epi( op(A)[M x K] op(B)[K x N] ), row-major FP32 storage:
 //   op(A)(m,k) = transA ? A[k*lda + m] : A[m*lda + k]
 //   op(B)(k,n) = transB ? B[n*ldb + k] : B[k*ldb + n]
 // epilogue (GemmArgs::epi): v = acc (+ C if accumulate) (+ bias[n]);
-//   kStore: C = v; kGelu: P = v, C = gelu(v); kGeluGrad: C = v * gelu'(P).
-// Workgroup: 256 threads = 4 waves, tile 64 x 64; wave w owns the 32 x 32
-// quadrant (w/2, w%2) as 2 x 2 MFMA blocks of 16 x 16.  LDS keeps A as
-// [64][32] and B transposed as [64][32] (both K-contiguous) so each lane's
-// operand is one 16-byte read.  Out-of-range rows/columns/k are zero-filled.
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
+//   kStore: C = v; kGelu: P = v (if P), C = gelu(v); kGeluGrad: C = v * gelu'(P).
+// Workgroup: 256 threads = 4 waves, tile kBM x kBN; wave w owns the
+// (kBM/2) x (kBN/2) quadrant (w/2, w%2) as 16 x 16 MFMA blocks.  LDS keeps A
+// as [kBM][32] and B transposed as [kBN][32] (both K-contiguous) so each
+// lane's operand is one 16-byte read.  With gridDim.z > 1 (split K) slice z
+// covers k in [z*kchunk, (z+1)*kchunk) and writes its raw sum to
+// part + z*M*N (the reduction applies the epilogue).
+template <int kBM, int kBN>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int kchunk, float* part)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 As[kTM][kTK];
-    __shared__ __attribute__((aligned(16))) __bf16 Bs[kTN][kTK];
+    __shared__ __attribute__((aligned(16))) __bf16 As[kBM][kLdsK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[kBN][kLdsK];
+    constexpr int kFM = kBM / 32, kFN = kBN / 32;  // 16 x 16 blocks per wave
     const int t = threadIdx.x;
     const int wave = t / 64, lane = t % 64;
-    const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
-    const int wm = (wave / 2) * 32, wn = (wave % 2) * 32;
-    f32x4 acc[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < g.K; k0 += kTK) {
-        // stage: each thread 8 elements of A and 8 of B
-        for (int e = 0; e < 8; ++e) {
-            const int idx = t * 8 + e;          // 0..2047 over a 64 x 32 tile
-            const int r = idx / kTK, kk = idx % kTK;
-            const int m = m0 + r, n = n0 + r, k = k0 + kk;
-            float av = 0.f, bv = 0.f;
-            if (m < g.M && k < g.K) av = g.transA ? g.A[(size_t)k * g.lda + m] : g.A[(size_t)m * g.lda + k];
-            if (n < g.N && k < g.K) bv = g.transB ? g.B[(size_t)n * g.ldb + k] : g.B[(size_t)k * g.ldb + n];
-            As[r][kk] = to_bf16(av);
-            Bs[r][kk] = to_bf16(bv);
-        }
+    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    const int wm = (wave / 2) * (kBM / 2), wn = (wave % 2) * (kBN / 2);
+    const int kb = blockIdx.z * kchunk, ke = min(g.K, kb + kchunk);
+    const bool vecA = (g.lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(g.A) & 15) == 0);
+    const bool vecB = (g.ldb % 4 == 0) && ((reinterpret_cast<uintptr_t>(g.B) & 15) == 0);
+    f32x4 acc[kFM][kFN];
+#pragma unroll
+    for (int a = 0; a < kFM; ++a)
+#pragma unroll
+        for (int b = 0; b < kFN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = kb; k0 < ke; k0 += kTK) {
+        stage_tile<kBM>(g.A, g.lda, !g.transA, g.M, ke, m0, k0, As, t, vecA);
+        stage_tile<kBN>(g.B, g.ldb, g.transB, g.N, ke, n0, k0, Bs, t, vecB);
         __syncthreads();
-        bf16x8 af[2], bfr[2];
-        for (int a = 0; a < 2; ++a) af[a] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * a + lane % 16][8 * (lane / 16)]);
-        for (int b = 0; b < 2; ++b) bfr[b] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 16 * b + lane % 16][8 * (lane / 16)]);
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+        bf16x8 af[kFM], bfr[kFN];
+#pragma unroll
+        for (int a = 0; a < kFM; ++a)
+            af[a] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * a + lane % 16][8 * (lane / 16)]);
+#pragma unroll
+        for (int b = 0; b < kFN; ++b)
+            bfr[b] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 16 * b + lane % 16][8 * (lane / 16)]);
+#pragma unroll
+        for (int a = 0; a < kFM; ++a)
+#pragma unroll
+            for (int b = 0; b < kFN; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
         __syncthreads();
     }
     // lane holds D[4*(lane/16)+e][lane%16] of each 16 x 16 block
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
+    float* slice = part ? part + (size_t)blockIdx.z * g.M * g.N : nullptr;
+#pragma unroll
+    for (int a = 0; a < kFM; ++a)
+#pragma unroll
+        for (int b = 0; b < kFN; ++b)
+#pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int m = m0 + wm + 16 * a + 4 * (lane / 16) + e;
                 const int n = n0 + wn + 16 * b + lane % 16;
                 if (m >= g.M || n >= g.N) continue;
-                const size_t o = (size_t)m * g.ldc + n;
                 float v = acc[a][b][e];
+                if (slice) {
+                    slice[(size_t)m * g.N + n] = v;
+                    continue;
+                }
+                const size_t o = (size_t)m * g.ldc + n;
                 if (g.accumulate) v += g.C[o];
                 if (g.bias) v += g.bias[n];
                 if (g.epi == kGelu) {
@@ -97,13 +172,38 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
             }
 }
 
-// out[n] = sum over m of X[m*ld + n] (bias gradients), fixed order per column.
-__global__ __launch_bounds__(256) void colsum_kernel(const float* X, int M, int N, int ld, float* out)
+// C = sum over slices z (in order) of part[z] (split-K reduction, kStore).
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* part, int splits, int M, int N, float* C,
+                                                            int ldc)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= M * N) return;
+    float v = 0.f;
+    for (int z = 0; z < splits; ++z) v += part[(size_t)z * M * N + i];
+    C[(size_t)(i / N) * ldc + i % N] = v;
+}
+
+// Bias gradients out[n] = sum over m of X[m*ld + n]: chunk c of 256 rows
+// sums its rows in order into part[c][n], then the chunks are added in order.
+constexpr int kColRows = 64;
+__global__ __launch_bounds__(256) void colsum_part_kernel(const float* X, int M, int N, int ld, float* part)
+{
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= N) return;
+    const int m0 = blockIdx.y * kColRows, m1 = min(M, m0 + kColRows);
+    float s = 0.f;
+#pragma unroll 16
+    for (int m = m0; m < m1; ++m) s += X[(size_t)m * ld + n];
+    part[(size_t)blockIdx.y * N + n] = s;
+}
+
+__global__ __launch_bounds__(256) void colsum_reduce_kernel(const float* part, int chunks, int N, float* out)
 {
     const int n = blockIdx.x * 256 + threadIdx.x;
     if (n >= N) return;
     float s = 0.f;
-    for (int m = 0; m < M; ++m) s += X[(size_t)m * ld + n];
+#pragma unroll 16
+    for (int c = 0; c < chunks; ++c) s += part[(size_t)c * N + n];
     out[n] = s;
 }
 
@@ -150,15 +250,39 @@ __global__ __launch_bounds__(256) void score_kernel(const float* out, int n, dou
 
 }  // namespace
 
-void launch_gemm(const GemmArgs& g, hipStream_t s)
+void launch_gemm(const GemmArgs& g, float* part, hipStream_t s)
 {
-    const dim3 grid((g.N + kTN - 1) / kTN, (g.M + kTM - 1) / kTM);
-    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, g);
+    if (g.M <= 0 || g.N <= 0) return;
+    const int64_t big = ((int64_t)(g.M + 127) / 128) * ((g.N + 127) / 128);
+    if (big >= 256) {
+        const dim3 grid((g.N + 127) / 128, (g.M + 127) / 128, 1);
+        hipLaunchKernelGGL((gemm_bf16_kernel<128, 128>), grid, dim3(256), 0, s, g, g.K, (float*)nullptr);
+        return;
+    }
+    const dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, 1);
+    const int tiles = (int)(grid.x * grid.y);
+    // split K for the few-tile, long-K products (weight gradients)
+    int splits = 1;
+    if (part && g.epi == kStore && !g.bias && !g.accumulate && g.ldc >= g.N) {
+        splits = std::min(std::min(kSplitMax, std::max(1, 512 / tiles)), std::max(1, g.K / 256));
+        if ((int64_t)splits * g.M * g.N > kSplitFloats) splits = (int)std::max<int64_t>(1, kSplitFloats / ((int64_t)g.M * g.N));
+    }
+    if (splits <= 1) {
+        hipLaunchKernelGGL((gemm_bf16_kernel<64, 64>), grid, dim3(256), 0, s, g, g.K, (float*)nullptr);
+        return;
+    }
+    const int kchunk = ((g.K + splits - 1) / splits + kTK - 1) / kTK * kTK;
+    splits = (g.K + kchunk - 1) / kchunk;
+    hipLaunchKernelGGL((gemm_bf16_kernel<64, 64>), dim3(grid.x, grid.y, splits), dim3(256), 0, s, g, kchunk, part);
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((g.M * g.N + 255) / 256), dim3(256), 0, s, part, splits, g.M, g.N,
+                       g.C, g.ldc);
 }
 
-void launch_colsum(const float* X, int M, int N, int ld, float* out, hipStream_t s)
+void launch_colsum(const float* X, int M, int N, int ld, float* out, float* part, hipStream_t s)
 {
-    hipLaunchKernelGGL(colsum_kernel, dim3((N + 255) / 256), dim3(256), 0, s, X, M, N, ld, out);
+    const int chunks = (M + kColRows - 1) / kColRows;
+    hipLaunchKernelGGL(colsum_part_kernel, dim3((N + 255) / 256, chunks), dim3(256), 0, s, X, M, N, ld, part);
+    hipLaunchKernelGGL(colsum_reduce_kernel, dim3((N + 255) / 256), dim3(256), 0, s, part, chunks, N, out);
 }
 
 void launch_mse_grad(const float* out, const float* y, int n, float* dout, float* se, hipStream_t s)
@@ -223,20 +347,20 @@ void mlp_forward(const float* params, const float* x, int n, MlpActs& s, hipStre
     g.bias = w.b1;
     g.epi = kGelu;
     g.P = s.a1;
-    launch_gemm(g, st);
+    launch_gemm(g, nullptr, st);
     g = gemm(s.h1, kH, false, w.W2, kH, true, s.h2, kH, n, kH, kH);
     g.bias = w.b2;
     g.epi = kGelu;
     g.P = s.a2;
-    launch_gemm(g, st);
+    launch_gemm(g, nullptr, st);
     g = gemm(s.h2, kH, false, w.W3, kH, true, s.h3, kH, n, kH, kH);
     g.bias = w.b3;
     g.epi = kGelu;
     g.P = s.a3;
-    launch_gemm(g, st);
+    launch_gemm(g, nullptr, st);
     g = gemm(s.h3, kH, false, w.W4, kH, true, s.out, kOut, n, kOut, kH);
     g.bias = w.b4;
-    launch_gemm(g, st);
+    launch_gemm(g, nullptr, st);
 }
 
 void mlp_infer(const float* params, const float* x, int n, float* hA, float* hB, float* out, hipStream_t st)
@@ -245,18 +369,18 @@ void mlp_infer(const float* params, const float* x, int n, float* hA, float* hB,
     GemmArgs g = gemm(x, kIn, false, w.W1, kIn, true, hA, kH, n, kH, kIn);
     g.bias = w.b1;
     g.epi = kGelu;
-    launch_gemm(g, st);
+    launch_gemm(g, nullptr, st);
     g = gemm(hA, kH, false, w.W2, kH, true, hB, kH, n, kH, kH);
     g.bias = w.b2;
     g.epi = kGelu;
-    launch_gemm(g, st);
+    launch_gemm(g, nullptr, st);
     g = gemm(hB, kH, false, w.W3, kH, true, hA, kH, n, kH, kH);
     g.bias = w.b3;
     g.epi = kGelu;
-    launch_gemm(g, st);
+    launch_gemm(g, nullptr, st);
     g = gemm(hA, kH, false, w.W4, kH, true, out, kOut, n, kOut, kH);
     g.bias = w.b4;
-    launch_gemm(g, st);
+    launch_gemm(g, nullptr, st);
 }
 
 // Backward from dout (n x 3) to the flat gradient (same layout as params).
@@ -266,29 +390,29 @@ void mlp_backward(const float* params, const float* x, int n, MlpActs& s, const 
     MlpView w = mlp_view(const_cast<float*>(params));
     MlpView gw = mlp_view(grad);
     // layer 4
-    launch_gemm(gemm(dout, kOut, true, s.h3, kH, false, gw.W4, kH, kOut, kH, n), st);
-    launch_colsum(dout, n, kOut, kOut, gw.b4, st);
+    launch_gemm(gemm(dout, kOut, true, s.h3, kH, false, gw.W4, kH, kOut, kH, n), s.part, st);
+    launch_colsum(dout, n, kOut, kOut, gw.b4, s.part, st);
     GemmArgs g = gemm(dout, kOut, false, w.W4, kH, false, s.d3, kH, n, kH, kOut);
     g.epi = kGeluGrad;
     g.P = s.a3;
-    launch_gemm(g, st);
+    launch_gemm(g, s.part, st);
     // layer 3
-    launch_gemm(gemm(s.d3, kH, true, s.h2, kH, false, gw.W3, kH, kH, kH, n), st);
-    launch_colsum(s.d3, n, kH, kH, gw.b3, st);
+    launch_gemm(gemm(s.d3, kH, true, s.h2, kH, false, gw.W3, kH, kH, kH, n), s.part, st);
+    launch_colsum(s.d3, n, kH, kH, gw.b3, s.part, st);
     g = gemm(s.d3, kH, false, w.W3, kH, false, s.d2, kH, n, kH, kH);
     g.epi = kGeluGrad;
     g.P = s.a2;
-    launch_gemm(g, st);
+    launch_gemm(g, s.part, st);
     // layer 2
-    launch_gemm(gemm(s.d2, kH, true, s.h1, kH, false, gw.W2, kH, kH, kH, n), st);
-    launch_colsum(s.d2, n, kH, kH, gw.b2, st);
+    launch_gemm(gemm(s.d2, kH, true, s.h1, kH, false, gw.W2, kH, kH, kH, n), s.part, st);
+    launch_colsum(s.d2, n, kH, kH, gw.b2, s.part, st);
     g = gemm(s.d2, kH, false, w.W2, kH, false, s.d1, kH, n, kH, kH);
     g.epi = kGeluGrad;
     g.P = s.a1;
-    launch_gemm(g, st);
+    launch_gemm(g, s.part, st);
     // layer 1
-    launch_gemm(gemm(s.d1, kH, true, x, kIn, false, gw.W1, kIn, kH, kIn, n), st);
-    launch_colsum(s.d1, n, kH, kH, gw.b1, st);
+    launch_gemm(gemm(s.d1, kH, true, x, kIn, false, gw.W1, kIn, kH, kIn, n), s.part, st);
+    launch_colsum(s.d1, n, kH, kH, gw.b1, s.part, st);
 }
 
 }  // namespace abcsmc

@@ -86,6 +86,7 @@ void carve_trainer(Carver& c, Trainer& t, int64_t rows, int64_t se_rows)
                    &t.acts.h3, &t.acts.d1, &t.acts.d2, &t.acts.d3};
     for (float** p : a) *p = c.take<float>((size_t)rows * kH);
     t.acts.out = c.take<float>((size_t)rows * kOut);
+    t.acts.part = c.take<float>((size_t)kSplitFloats);
 }
 
 // `epochs` passes of minibatch Adam over (X, Y) (n rows, in order; the last
@@ -140,7 +141,7 @@ abcsmc_surrogate_config with_defaults(const abcsmc_surrogate_config* in)
     if (c.n_train == 0) c.n_train = (int64_t)1 << 20;
     if (c.epochs == 0) c.epochs = 4;
     else if (c.epochs < 0) c.epochs = 0;
-    if (c.batch == 0) c.batch = 1024;
+    if (c.batch == 0) c.batch = 8192;
     if (c.lr == 0.0) c.lr = 1e-3;
     if (c.keep_frac == 0.0) c.keep_frac = 0.1;
     if (c.audit_rho == 0.0) c.audit_rho = 0.01;
@@ -489,19 +490,28 @@ int abcsmc_surrogate_enable(abcsmc_ctx* x, const abcsmc_surrogate_config* scfg)
     TrainDataArgs ta{x->model, x->at<double>(x->L.obs), c.n_train, S->tx, S->ty};
     launch_train_data(ta, s);
     HIPCHK(x, hipGetLastError());
-    std::vector<double> losses((size_t)std::max(c.epochs, 1), 0.0);
-    HIPCHK(x, train_epochs(S->tr, S->tx, S->ty, c.n_train, c.batch, c.epochs, (float)c.lr, losses.data(), s));
+    HIPCHK(x, hipEventRecord(S->ev[1], s));
+    // the loss is read back only after the first and the last pass
+    std::vector<double> losses(2, 0.0);
+    for (int32_t e = 0; e < c.epochs; ++e) {
+        double* le = (e == 0) ? &losses[0] : (e == c.epochs - 1 ? &losses[1] : nullptr);
+        HIPCHK(x, train_epochs(S->tr, S->tx, S->ty, c.n_train, c.batch, 1, (float)c.lr, le, s));
+    }
+    HIPCHK(x, hipEventRecord(S->ev[2], s));
     HIPCHK(x, hipMemcpyAsync(S->params0, S->tr.params, kMlpParams * sizeof(float), hipMemcpyDeviceToDevice, s));
     HIPCHK(x, hipMemcpyAsync(S->am0, S->tr.am, kMlpParams * sizeof(float), hipMemcpyDeviceToDevice, s));
     HIPCHK(x, hipMemcpyAsync(S->av0, S->tr.av, kMlpParams * sizeof(float), hipMemcpyDeviceToDevice, s));
-    HIPCHK(x, hipEventRecord(S->ev[1], s));
     HIPCHK(x, hipStreamSynchronize(s));
     S->step0 = S->tr.step;
     S->info = abcsmc_surrogate_info{};
-    S->info.loss_first = c.epochs ? losses.front() : 0.0;
-    S->info.loss_last = c.epochs ? losses[(size_t)c.epochs - 1] : 0.0;
+    S->info.loss_first = c.epochs ? losses[0] : 0.0;
+    S->info.loss_last = c.epochs ? (c.epochs == 1 ? losses[0] : losses[1]) : 0.0;
     S->info.train_steps = S->tr.step;
-    S->info.ms_train = elapsed(S->ev[0], S->ev[1]);
+    S->info.ms_data = elapsed(S->ev[0], S->ev[1]);
+    S->info.ms_train = elapsed(S->ev[1], S->ev[2]);
+    // multiply-adds per sample: 8*256 + 256*256 * 2 + 256*3
+    const double macs = (double)kIn * kH + 2.0 * kH * kH + (double)kH * kOut;
+    S->info.train_flops = (int64_t)(2.0 * 3.0 * macs * (double)c.n_train * (double)c.epochs);
     S->info.active = 1;
     S->info.round = -1;
     // the population of the last completed stage has no audit acceptances

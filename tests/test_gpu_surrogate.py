@@ -179,7 +179,7 @@ def test_trained_network_enriches_more_than_random():
     for name, epochs in (("trained", 6), ("random", -1)):
         with A.Context(w, obs) as ctx:
             ctx.round()
-            ctx.surrogate_enable(n_train=32768, epochs=epochs, keep_frac=0.2, audit_rho=0.1, pool=8192,
+            ctx.surrogate_enable(n_train=32768, epochs=epochs, batch=512, keep_frac=0.2, audit_rho=0.1, pool=8192,
                                  tune_rows=-1, fn_max=1.0, seed=5)
             ctx.round()
             res[name] = ctx.surrogate_info()

@@ -205,7 +205,7 @@ typedef struct {
 } abcsmc_schedule;
 
 int abcsmc_batch_workspace_size(const abcsmc_config* cfgs, int32_t n_runs, size_t* bytes);
-/* obs[r]: (T_r+1) x 3 int64 of run r; copied.  1 <= n_runs <= 4096, N_r <= 2^20. */
+/* obs[r]: (T_r+1) x 3 int64 of run r; copied.  1 <= n_runs <= 4096, N_r <= 2^20, sum of N_r <= 2^26. */
 int abcsmc_batch_init(const abcsmc_config* cfgs, int32_t n_runs, const int64_t* const* obs, abcsmc_batch** out);
 int abcsmc_batch_set_schedule(abcsmc_batch* b, const abcsmc_schedule* s);
 int abcsmc_batch_get_schedule(const abcsmc_batch* b, abcsmc_schedule* s);

@@ -52,6 +52,8 @@ struct BRun {
     double* red_d;             // 1 x res_nblk
     int32_t res_blk0;          // first block of this run in the segmented resample grid
     int32_t res_nblk;
+    int32_t off;               // first slot of this run in the batch-wide sort arrays (sum of earlier N)
+    int32_t rb0;               // first 256-row block of this run in the finalize / window tables
 };
 
 // Mutable state of one run (device).
@@ -66,8 +68,10 @@ struct BState {
     int32_t failed;    // 1 once a stage ran out of proposals (run frozen)
     int32_t cur;       // population buffer of the last completed stage
     int32_t nxt;       // buffer the current stage writes
+    int32_t dstar;     // sort coordinate of the weight window (largest column variance)
+    int32_t pad_;
     unsigned long long issued, completed, done_acc, accepted, proposals, invalid, attempts, days,
-        survivors, fallback, limit, stages_done;
+        survivors, fallback, limit, stages_done, terms;
 };
 
 struct BGlobal {
@@ -89,6 +93,15 @@ struct BatchArgs {
     int32_t n_res_blocks, n_w_blocks, n_fin_blocks;
     int32_t propose_blocks;
     double ex[7];              // table-exp constants (as WeightArgs::ex)
+    // weight window (batch-wide arrays; run r owns slots [off_r, off_r + N_r))
+    unsigned long long* colkeys;  // npad: (run, column key, column) sorted
+    unsigned long long* rowkeys;  // npad: (run, sigma octave, row key, row) sorted
+    double* scols;             // n_total x 9 sorted columns (u_k, q_k)
+    double* skey;              // n_total sorted sort-coordinate values
+    int2* win;                 // per 256-row block: column window [x, y) within the run
+    size_t npad;               // power-of-two sort length >= n_total
+    int32_t n_total;           // sum of N_r
+    int32_t n_key_blocks;      // ceil(npad / 256)
 };
 
 void batch_launch_stage(const BatchArgs& a, bool stage0, hipStream_t s);

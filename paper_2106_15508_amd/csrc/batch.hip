@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void begin_kernel(BatchArgs a)
         }
         S.nxt = stage == 0 ? 0 : 1 - S.cur;
         S.issued = S.completed = S.done_acc = S.accepted = S.proposals = 0;
-        S.invalid = S.attempts = S.days = S.survivors = S.fallback = 0;
+        S.invalid = S.attempts = S.days = S.survivors = S.fallback = S.terms = 0;
         const double rate = S.rate > 0.01 ? S.rate : 0.01;
         unsigned long long lim = stage == 0
                                      ? (unsigned long long)((R.N + kChunkP - 1) / kChunkP)
@@ -438,46 +438,197 @@ __global__ __launch_bounds__(kBlock) void bcompact_scatter_kernel(BatchArgs a)
 
 // ------------------------------------------------------------------ weights
 
+// Weight window, per run (as the single-run pass): the sort coordinate d* of
+// largest column variance; columns sorted by (run, u_{k,d*}); rows sorted by
+// (run, sigma octave, u_{j,d*}); each 256-row block gets the column range
+// |u_{k,d*} - u_{j,d*}| <= kWindow sigma_j of its rows.  One batch-wide bitonic
+// sort per key set: the run index in the top 12 bits keeps every run's keys in
+// its own slot range [off_r, off_r + N_r).
+using wterm::coord_key32;
+using wterm::kWindow;
+using wterm::lower_index;
+using wterm::sigma_octave;
+using wterm::wave_max;
+using wterm::wave_min;
+
+// One block per run: variance of each coordinate over the run's columns.
+__global__ __launch_bounds__(kBlock) void bwdim_kernel(BatchArgs a)
+{
+    __shared__ double sh[kBlock];
+    const BRun& R = a.runs[blockIdx.x];
+    BState& S = a.st[blockIdx.x];
+    if (S.failed) return;
+    const int M = (int)S.survivors;
+    double best = -1.0;
+    int bd = 0;
+    for (int d = 0; d < kNP; ++d) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int k = threadIdx.x; k < M; k += kBlock) {
+            const double v = R.cols[(size_t)k * 9 + d];
+            s1 += v;
+            s2 += v * v;
+        }
+        s1 = bsum(s1, sh);
+        s2 = bsum(s2, sh);
+        const double mean = s1 / (double)M;
+        const double var = s2 / (double)M - mean * mean;
+        if (var > best) {
+            best = var;
+            bd = d;
+        }
+    }
+    if (threadIdx.x == 0) S.dstar = bd;
+}
+
+// run owning batch-wide slot i (i < n_total)
+__device__ __forceinline__ int slot_run(const BatchArgs& a, int i)
+{
+    int lo = 0, hi = a.n_runs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.runs[mid].off <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void bkeys_kernel(BatchArgs a)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.npad) return;
+    if (i >= (size_t)a.n_total) {
+        a.colkeys[i] = ~0ull;
+        a.rowkeys[i] = ~0ull;
+        return;
+    }
+    const int r = slot_run(a, (int)i);
+    const BRun& R = a.runs[r];
+    const BState& S = a.st[r];
+    const unsigned long long k = (unsigned long long)((int)i - R.off);
+    const unsigned long long run = (unsigned long long)r << 52;
+    if (S.failed) {
+        a.colkeys[i] = run | (0xFFFFFFFFull << 20) | k;
+        a.rowkeys[i] = run | k;
+        return;
+    }
+    const int ds = S.dstar;
+    a.colkeys[i] = (k < (unsigned long long)S.survivors)
+                       ? run | (coord_key32(R.cols[k * 9 + ds]) << 20) | k
+                       : run | (0xFFFFFFFFull << 20) | k;
+    const int nx = S.nxt;
+    a.rowkeys[i] = run | (sigma_octave(R.sigma[nx][k]) << 46) | ((coord_key32(R.u[nx][k * kNP + ds]) >> 6) << 20) | k;
+}
+
+__global__ __launch_bounds__(kBlock) void bcolgather_kernel(BatchArgs a)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.n_total) return;
+    const int r = slot_run(a, i);
+    const BRun& R = a.runs[r];
+    const BState& S = a.st[r];
+    if (S.failed || i - R.off >= (int)S.survivors) return;
+    const size_t src = (size_t)(a.colkeys[i] & 0xFFFFFull);
+    const double* c = R.cols + src * 9;
+    double* o = a.scols + (size_t)i * 9;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) o[d] = c[d];
+    a.skey[i] = c[S.dstar];
+}
+
+// One block per (run, 256 sorted rows): the block's column window.
+__global__ __launch_bounds__(kBlock) void bwindow_kernel(BatchArgs a)
+{
+    __shared__ double slo[kBlock / kWave], shi[kBlock / kWave];
+    const int2 fb = a.fin_tab[blockIdx.x];
+    const BRun& R = a.runs[fb.x];
+    const BState& S = a.st[fb.x];
+    if (S.failed) return;
+    const int nx = S.nxt;
+    const int rr = fb.y * kBlock + threadIdx.x;
+    double lo = __builtin_inf(), hi = -__builtin_inf();
+    if (rr < R.N) {
+        const size_t j = (size_t)(a.rowkeys[R.off + rr] & 0xFFFFFull);
+        const double W = kWindow * R.sigma[nx][j];
+        const double x = R.u[nx][j * kNP + S.dstar];
+        lo = x - W;
+        hi = x + W;
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        slo[threadIdx.x / kWave] = lo;
+        shi[threadIdx.x / kWave] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < kBlock / kWave; ++q) {
+            lo = slo[q] < lo ? slo[q] : lo;
+            hi = shi[q] > hi ? shi[q] : hi;
+        }
+        const int M = (int)S.survivors;
+        const double* sk = a.skey + R.off;
+        a.win[R.rb0 + fb.y] = make_int2(lower_index(sk, M, lo, false), lower_index(sk, M, hi, true));
+    }
+}
+
+// grid = weight table (run, row block, chunk): chunk c of the block's window,
+// sorted rows; partial sums go to the rows' own indices (finalize unchanged).
 __global__ __launch_bounds__(kBlock) void bweights_kernel(BatchArgs a)
 {
     __shared__ double tu[kNP][wterm::kTile];
     __shared__ double tq[wterm::kTile];
     __shared__ double T[64];
-    if (threadIdx.x < 64) T[threadIdx.x] = wterm::table_entry(threadIdx.x);
     const int4 wb = a.w_tab[blockIdx.x];
     const BRun& R = a.runs[wb.x];
     const BState& S = a.st[wb.x];
     if (S.failed) return;  // uniform across the block
     const int nx = S.nxt;
-    const int j = wb.y * kBlock + threadIdx.x;
-    const bool active = j < R.N;
+    const int rr = wb.y * kBlock + threadIdx.x;
+    const bool active = rr < R.N;
+    const size_t j = active ? (size_t)(a.rowkeys[R.off + rr] & 0xFFFFFull) : 0;
+    const int2 wnd = a.win[R.rb0 + wb.y];
+    const int len = wnd.y - wnd.x > 0 ? wnd.y - wnd.x : 0;
+    const int Sc = R.wchunks, c = wb.z;
+    const int k0 = wnd.x + (int)(((long long)len * c) / Sc);
+    const int k1 = wnd.x + (int)(((long long)len * (c + 1)) / Sc);
+    if (k0 >= k1) {
+        if (active) R.wpart[(size_t)c * R.N + j] = 0.0;
+        return;
+    }
+    if (threadIdx.x < 64) T[threadIdx.x] = wterm::table_entry(threadIdx.x);
+    const int ds = S.dstar;
     double uj[kNP];
-    double ninv = 0.0;
+    double ninv = 0.0, lo = __builtin_inf(), hi = -__builtin_inf();
     if (active) {
 #pragma unroll
-        for (int d = 0; d < kNP; ++d) uj[d] = R.u[nx][(size_t)j * kNP + d];
+        for (int d = 0; d < kNP; ++d) uj[d] = R.u[nx][j * kNP + d];
         const double sj = R.sigma[nx][j];
         ninv = -1.0 / (2.0 * (sj * sj));
+        lo = uj[ds] - kWindow * sj;
+        hi = uj[ds] + kWindow * sj;
     } else {
 #pragma unroll
         for (int d = 0; d < kNP; ++d) uj[d] = 0.0;
     }
-    const int M = (int)S.survivors;
-    const int nt = (M + wterm::kTile - 1) / wterm::kTile;
-    const int Sc = R.wchunks, c = wb.z;
-    const int t0 = (int)(((long long)nt * c) / Sc), t1 = (int)(((long long)nt * (c + 1)) / Sc);
+    const double wlo = wave_min(lo), whi = wave_max(hi);
+    const unsigned long long lanes = (unsigned long long)__popcll(__ballot(active));
+    unsigned long long evaluated = 0;
+    const double* scols = a.scols + (size_t)R.off * 9;
+    const double* skey = a.skey + R.off;
     double total = 0.0;
-    for (int tile = t0; tile < t1; ++tile) {
-        const int c0 = tile * wterm::kTile;
-        const int n = min(wterm::kTile, M - c0);
+    for (int c0 = k0; c0 < k1; c0 += wterm::kTile) {
+        const int n = min(wterm::kTile, k1 - c0);
         __syncthreads();
         if (threadIdx.x < n) {
-            const double* col = R.cols + (size_t)(c0 + threadIdx.x) * 9;
+            const double* col = scols + (size_t)(c0 + threadIdx.x) * 9;
 #pragma unroll
             for (int d = 0; d < kNP; ++d) tu[d][threadIdx.x] = col[d];
             tq[threadIdx.x] = col[8];
         }
         __syncthreads();
+        // this wave's rows cannot reach the tile: every term is exactly zero
+        if (skey[c0 + n - 1] < wlo || skey[c0] > whi) continue;
+        evaluated += lanes * (unsigned long long)n;
         double p0 = 0.0, p1 = 0.0;
         int cc = 0;
         for (; cc + 1 < n; cc += 2) {
@@ -488,6 +639,7 @@ __global__ __launch_bounds__(kBlock) void bweights_kernel(BatchArgs a)
         total += p0 + p1;
     }
     if (active) R.wpart[(size_t)c * R.N + j] = total;
+    if ((threadIdx.x & (kWave - 1)) == 0 && evaluated) atomicAdd(&a.st[wb.x].terms, evaluated);
 }
 
 __global__ __launch_bounds__(kBlock) void bfinalize_kernel(BatchArgs a)
@@ -635,6 +787,12 @@ void batch_launch_stage(const BatchArgs& a, bool stage0, hipStream_t s)
     hipLaunchKernelGGL(bcompact_scan_kernel, dim3(a.n_runs), b, 0, s, a);
     hipLaunchKernelGGL(bcompact_scatter_kernel, dim3(a.max_cap_chunks, a.n_runs), b, 0, s, a);
     if (!stage0) {
+        hipLaunchKernelGGL(bwdim_kernel, dim3(a.n_runs), b, 0, s, a);
+        hipLaunchKernelGGL(bkeys_kernel, dim3(a.n_key_blocks), b, 0, s, a);
+        launch_sort_u64(a.colkeys, a.npad, s);
+        launch_sort_u64(a.rowkeys, a.npad, s);
+        hipLaunchKernelGGL(bcolgather_kernel, dim3((a.n_total + kBlock - 1) / kBlock), b, 0, s, a);
+        hipLaunchKernelGGL(bwindow_kernel, dim3(a.n_fin_blocks), b, 0, s, a);
         hipLaunchKernelGGL(bweights_kernel, dim3(a.n_w_blocks), b, 0, s, a);
         hipLaunchKernelGGL(bfinalize_kernel, dim3(a.n_fin_blocks), b, 0, s, a);
     }

@@ -92,6 +92,31 @@ RunLayout run_layout(const abcsmc_config& c, size_t o)
     return L;
 }
 
+// Batch-wide weight-window arrays after the tables: column and row sort keys
+// (power-of-two length), sorted columns, their sort-coordinate values, and
+// one window per 256-row block.
+struct WinLayout {
+    size_t colkeys, rowkeys, scols, skey, win, end, npad;
+};
+
+WinLayout win_layout(size_t o, size_t n_total, size_t n_fin)
+{
+    WinLayout L{};
+    L.npad = sort_padded_size(n_total);
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = al(o + bytes);
+        return at;
+    };
+    L.colkeys = take(L.npad * 8);
+    L.rowkeys = take(L.npad * 8);
+    L.scols = take(n_total * 9 * 8);
+    L.skey = take(n_total * 8);
+    L.win = take(n_fin * sizeof(int2));
+    L.end = o;
+    return L;
+}
+
 // validation shared with the single-run path's rules (subset relevant here)
 int bvalidate(const abcsmc_config& c, const int64_t* obs, std::string* e)
 {
@@ -305,6 +330,10 @@ int abcsmc_batch_workspace_size(const abcsmc_config* cfgs, int32_t n_runs, size_
     o = al(o + (size_t)n_res * sizeof(int2));
     o = al(o + (size_t)n_w * sizeof(int4));
     o = al(o + (size_t)n_fin * sizeof(int2));
+    size_t n_total = 0;
+    for (int r = 0; r < n_runs; ++r) n_total += (size_t)cfgs[r].n_particles;
+    if (n_total > ((size_t)1 << 26)) return bfail(nullptr, ABCSMC_EINVAL, "batched runs: sum of N <= 2^26");
+    o = win_layout(o, n_total, (size_t)n_fin).end;
     *bytes = o;
     return ABCSMC_OK;
 }
@@ -354,7 +383,7 @@ int abcsmc_batch_init(const abcsmc_config* cfgs, int32_t n_runs, const int64_t* 
     if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess)
         return bail(ABCSMC_EDEVICE, "hipEventCreate failed");
     // per-run regions and descriptors
-    size_t o = 0;
+    size_t o = 0, n_total = 0;
     std::vector<int2> res_tab, fin_tab;
     b->runs.resize(n_runs);
     for (int r = 0; r < n_runs; ++r) {
@@ -410,6 +439,9 @@ int abcsmc_batch_init(const abcsmc_config* cfgs, int32_t n_runs, const int64_t* 
         R.wave_off = (uint32_t*)(w + L.woff);
         R.red_u = (unsigned long long*)(w + L.red_u);
         R.red_d = (double*)(w + L.red_d);
+        R.off = (int32_t)n_total;
+        R.rb0 = (int32_t)fin_tab.size();
+        n_total += (size_t)c.n_particles;
         R.res_blk0 = (int32_t)res_tab.size();
         R.res_nblk = (int32_t)((c.n_particles + 1023) / 1024);
         for (int k = 0; k < R.res_nblk; ++k) res_tab.push_back(make_int2(r, k));
@@ -436,6 +468,8 @@ int abcsmc_batch_init(const abcsmc_config* cfgs, int32_t n_runs, const int64_t* 
     o = al(o + (size_t)b->max_w_blocks * sizeof(int4));
     b->off_fin = o;
     o = al(o + fin_tab.size() * sizeof(int2));
+    const WinLayout WL = win_layout(o, n_total, fin_tab.size());
+    o = WL.end;
     if (o > bytes) return bail(ABCSMC_EINVAL, "internal layout mismatch");
     if (hipMemcpy(b->ws + b->off_res, res_tab.data(), res_tab.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->ws + b->off_fin, fin_tab.data(), fin_tab.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
@@ -454,6 +488,14 @@ int abcsmc_batch_init(const abcsmc_config* cfgs, int32_t n_runs, const int64_t* 
     A.max_cap_chunks = b->max_cap_chunks;
     A.n_res_blocks = b->n_res;
     A.n_fin_blocks = b->n_fin;
+    A.colkeys = (unsigned long long*)(b->ws + WL.colkeys);
+    A.rowkeys = (unsigned long long*)(b->ws + WL.rowkeys);
+    A.scols = (double*)(b->ws + WL.scols);
+    A.skey = (double*)(b->ws + WL.skey);
+    A.win = (int2*)(b->ws + WL.win);
+    A.npad = WL.npad;
+    A.n_total = (int32_t)n_total;
+    A.n_key_blocks = (int32_t)((WL.npad + kBlock - 1) / kBlock);
     weight_exp_constants(A.ex);
     default_schedule(b->sched);
     if ((rc = apply_schedule(b)) || (rc = initial_states(b))) {
@@ -535,6 +577,7 @@ int abcsmc_batch_round(abcsmc_batch* b, abcsmc_round_info* infos)
             I.ms_total = ms;
             I.sim_days = (int64_t)S.days;
             I.weight_pairs = stage == 0 ? 0 : (int64_t)b->cfgs[r].n_particles * (int64_t)S.survivors;
+            I.weight_terms = (int64_t)S.terms;
         }
     }
     return ABCSMC_OK;

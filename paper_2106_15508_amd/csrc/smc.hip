@@ -237,6 +237,12 @@ __global__ __launch_bounds__(kBlock) void resample_write_kernel(ResampleArgs a)
 // ---------------------------------------------------------------------------
 using wterm::kTile;
 using wterm::pair_term;
+using wterm::coord_key32;
+using wterm::kWindow;
+using wterm::lower_index;
+using wterm::sigma_octave;
+using wterm::wave_max;
+using wterm::wave_min;
 
 // ---- windowed evaluation -------------------------------------------------
 // A term is exactly zero (exponent below -708) once |u_jd - u_kd| exceeds
@@ -250,7 +256,6 @@ using wterm::pair_term;
 // also skips tiles outside its own window.
 
 constexpr int kDimBlocks = 256;
-constexpr double kWindow = 37.7;
 
 __global__ __launch_bounds__(kBlock) void wdim_partial_kernel(WeightArgs a)
 {
@@ -296,12 +301,6 @@ __global__ __launch_bounds__(kBlock) void wdim_pick_kernel(WeightArgs a)
     if (threadIdx.x == 0) *a.dstar = bd;
 }
 
-__device__ __forceinline__ unsigned long long coord_key32(double u)
-{
-    const double c = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
-    return (unsigned long long)(unsigned int)(c * 4294967295.0);
-}
-
 __global__ __launch_bounds__(kBlock) void wcolkeys_kernel(WeightArgs a)
 {
     const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
@@ -334,43 +333,8 @@ __global__ __launch_bounds__(kBlock) void wrowkeys_kernel(WeightArgs a)
         return;
     }
     const int ds = *a.dstar;
-    int e;
-    (void)__builtin_frexp(a.sigma[i], &e);
-    int oct = e + 40;
-    oct = oct < 0 ? 0 : (oct > 63 ? 63 : oct);
-    const unsigned long long hi = ((unsigned long long)oct << 26) | (coord_key32(a.u[i * kNP + ds]) >> 6);
+    const unsigned long long hi = (sigma_octave(a.sigma[i]) << 26) | (coord_key32(a.u[i * kNP + ds]) >> 6);
     a.rowkeys[i] = (hi << 32) | (unsigned long long)i;
-}
-
-// first index in sorted v[0..n) with v >= x (or > x when strict)
-__device__ __forceinline__ int lower_index(const double* v, int n, double x, bool strict)
-{
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (strict ? (v[mid] <= x) : (v[mid] < x)) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ double wave_min(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const double o = __shfl_xor(v, off, kWave);
-        v = o < v ? o : v;
-    }
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const double o = __shfl_xor(v, off, kWave);
-        v = o > v ? o : v;
-    }
-    return v;
 }
 
 // Window of each row block (256 consecutive sorted rows): the sorted column

@@ -34,11 +34,12 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
-# FP64 flops (fma = 2) of one importance-weight term: 8 differences, 8 fma
-# for the squared distance, 1 scaling, table exp (18: scale and round 2,
-# two-part reduction 4, degree-5 polynomial 10, table product 1, 2^k 1),
-# weight product 1, accumulation 1.
-FLOPS_PER_PAIR = 8 + 16 + 1 + 18 + 1 + 1
+# FP64 flops of one importance-weight term as the kernel evaluates it (every
+# FP64 instruction counted, fma = 2): 8 differences, 8 fma for the squared
+# distance, exponent scaling 1, table exp 12 (round 1, reduction 2, integer
+# conversion 1, 3 fma 6, table product 1, 2^k 1), weight product 1,
+# accumulation 1.
+FLOPS_PER_PAIR = 8 + 16 + 1 + 12 + 1 + 1
 
 # HBM bytes per launch of the dominant kernel measured with rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE on this workload, scaled by the counters' reading

@@ -575,9 +575,7 @@ __global__ __launch_bounds__(kBlock) void bwindow_kernel(BatchArgs a)
 // sorted rows; partial sums go to the rows' own indices (finalize unchanged).
 __global__ __launch_bounds__(kBlock) void bweights_kernel(BatchArgs a)
 {
-    __shared__ double tu[kNP][wterm::kTile];
-    __shared__ double tq[wterm::kTile];
-    __shared__ double T[64];
+    __shared__ double T[wterm::kTab];
     const int4 wb = a.w_tab[blockIdx.x];
     const BRun& R = a.runs[wb.x];
     const BState& S = a.st[wb.x];
@@ -595,15 +593,16 @@ __global__ __launch_bounds__(kBlock) void bweights_kernel(BatchArgs a)
         if (active) R.wpart[(size_t)c * R.N + j] = 0.0;
         return;
     }
-    if (threadIdx.x < 64) T[threadIdx.x] = wterm::table_entry(threadIdx.x);
+    wterm::fill_table(T);
+    __syncthreads();
     const int ds = S.dstar;
     double uj[kNP];
-    double ninv = 0.0, lo = __builtin_inf(), hi = -__builtin_inf();
+    double cj = 0.0, lo = __builtin_inf(), hi = -__builtin_inf();
     if (active) {
 #pragma unroll
         for (int d = 0; d < kNP; ++d) uj[d] = R.u[nx][j * kNP + d];
         const double sj = R.sigma[nx][j];
-        ninv = -1.0 / (2.0 * (sj * sj));
+        cj = wterm::row_scale(sj, a.ex);
         lo = uj[ds] - kWindow * sj;
         hi = uj[ds] + kWindow * sj;
     } else {
@@ -613,31 +612,9 @@ __global__ __launch_bounds__(kBlock) void bweights_kernel(BatchArgs a)
     const double wlo = wave_min(lo), whi = wave_max(hi);
     const unsigned long long lanes = (unsigned long long)__popcll(__ballot(active));
     unsigned long long evaluated = 0;
-    const double* scols = a.scols + (size_t)R.off * 9;
-    const double* skey = a.skey + R.off;
-    double total = 0.0;
-    for (int c0 = k0; c0 < k1; c0 += wterm::kTile) {
-        const int n = min(wterm::kTile, k1 - c0);
-        __syncthreads();
-        if (threadIdx.x < n) {
-            const double* col = scols + (size_t)(c0 + threadIdx.x) * 9;
-#pragma unroll
-            for (int d = 0; d < kNP; ++d) tu[d][threadIdx.x] = col[d];
-            tq[threadIdx.x] = col[8];
-        }
-        __syncthreads();
-        // this wave's rows cannot reach the tile: every term is exactly zero
-        if (skey[c0 + n - 1] < wlo || skey[c0] > whi) continue;
-        evaluated += lanes * (unsigned long long)n;
-        double p0 = 0.0, p1 = 0.0;
-        int cc = 0;
-        for (; cc + 1 < n; cc += 2) {
-            p0 += wterm::pair_term(uj, ninv, tu, tq, cc, T, a.ex);
-            p1 += wterm::pair_term(uj, ninv, tu, tq, cc + 1, T, a.ex);
-        }
-        if (cc < n) p0 += wterm::pair_term(uj, ninv, tu, tq, cc, T, a.ex);
-        total += p0 + p1;
-    }
+    const double total = wterm::row_sum(uj, cj, (wterm::const_col_ptr)(a.scols + (size_t)R.off * 9),
+                                        (wterm::const_col_ptr)(a.skey + R.off), k0, k1, wlo, whi, T, a.ex, lanes,
+                                        evaluated);
     if (active) R.wpart[(size_t)c * R.N + j] = total;
     if ((threadIdx.x & (kWave - 1)) == 0 && evaluated) atomicAdd(&a.st[wb.x].terms, evaluated);
 }

@@ -236,7 +236,6 @@ __global__ __launch_bounds__(kBlock) void resample_write_kernel(ResampleArgs a)
 // to; the trajectories never use it.
 // ---------------------------------------------------------------------------
 using wterm::kTile;
-using wterm::pair_term;
 using wterm::coord_key32;
 using wterm::kWindow;
 using wterm::lower_index;
@@ -376,9 +375,7 @@ __global__ __launch_bounds__(kBlock) void wwindow_kernel(WeightArgs a)
 // the window write zero partials and leave.
 __global__ __launch_bounds__(kBlock) void weights_kernel(WeightArgs a)
 {
-    __shared__ double tu[kNP][kTile];
-    __shared__ double tq[kTile];
-    __shared__ double T[64];
+    __shared__ double T[wterm::kTab];
     const int r = blockIdx.x * kBlock + threadIdx.x;   // sorted row position
     const bool active = r < a.N;
     const int2 wnd = a.win[blockIdx.x];
@@ -388,16 +385,17 @@ __global__ __launch_bounds__(kBlock) void weights_kernel(WeightArgs a)
         if (active) a.partial[(size_t)blockIdx.y * a.N + r] = 0.0;
         return;
     }
-    if (threadIdx.x < 64) T[threadIdx.x] = wterm::table_entry(threadIdx.x);  // 2^(i/64)
+    wterm::fill_table(T);
+    __syncthreads();
     const int ds = *a.dstar;
     double uj[kNP];
-    double ninv = 0.0, lo = __builtin_inf(), hi = -__builtin_inf();
+    double cj = 0.0, lo = __builtin_inf(), hi = -__builtin_inf();
     if (active) {
         const size_t j = (size_t)(a.rowkeys[r] & 0xFFFFFFFFull);
 #pragma unroll
         for (int d = 0; d < kNP; ++d) uj[d] = a.u[j * kNP + d];
         const double sj = a.sigma[j];
-        ninv = -1.0 / (2.0 * (sj * sj));
+        cj = wterm::row_scale(sj, a.ex);
         const double R = kWindow * sj;
         lo = uj[ds] - R;
         hi = uj[ds] + R;
@@ -408,29 +406,10 @@ __global__ __launch_bounds__(kBlock) void weights_kernel(WeightArgs a)
     const double wlo = wave_min(lo), whi = wave_max(hi);
     const unsigned long long lanes = (unsigned long long)__popcll(__ballot(active));
     unsigned long long evaluated = 0;
-    double total = 0.0;
-    for (int c0 = k0; c0 < k1; c0 += kTile) {
-        const int n = min(kTile, k1 - c0);
-        __syncthreads();
-        if (threadIdx.x < n) {
-            const double* col = a.scols + (size_t)(c0 + threadIdx.x) * 9;
-#pragma unroll
-            for (int d = 0; d < kNP; ++d) tu[d][threadIdx.x] = col[d];
-            tq[threadIdx.x] = col[8];
-        }
-        __syncthreads();
-        // this wave's rows cannot reach the tile: every term is exactly zero
-        if (a.skey[c0 + n - 1] < wlo || a.skey[c0] > whi) continue;
-        evaluated += lanes * (unsigned long long)n;
-        double p0 = 0.0, p1 = 0.0;
-        int cc = 0;
-        for (; cc + 1 < n; cc += 2) {
-            p0 += pair_term(uj, ninv, tu, tq, cc, T, a.ex);
-            p1 += pair_term(uj, ninv, tu, tq, cc + 1, T, a.ex);
-        }
-        if (cc < n) p0 += pair_term(uj, ninv, tu, tq, cc, T, a.ex);
-        total += p0 + p1;
-    }
+    // read-only for the whole launch: constant address space, so the
+    // wave-uniform column reads become scalar loads
+    const double total = wterm::row_sum(uj, cj, (wterm::const_col_ptr)a.scols, (wterm::const_col_ptr)a.skey, k0,
+                                        k1, wlo, whi, T, a.ex, lanes, evaluated);
     if (active) a.partial[(size_t)blockIdx.y * a.N + r] = total;
     if ((threadIdx.x & (kWave - 1)) == 0 && evaluated) atomicAdd(a.terms, evaluated);
 }
@@ -650,13 +629,11 @@ inline unsigned blocks_of(int64_t n, int per) { return (unsigned)((n + per - 1) 
 
 void weight_exp_constants(double ex[7])
 {
-    ex[0] = 92.332482616893658;           // 64 / ln 2
-    ex[1] = dm::kLn2Hi / 64.0;            // exact scaling of the two-part ln 2
-    ex[2] = dm::kLn2Lo / 64.0;
-    ex[3] = 1.0 / 2.0;
-    ex[4] = 1.0 / 6.0;
-    ex[5] = 1.0 / 24.0;
-    ex[6] = 1.0 / 120.0;
+    ex[0] = 0.6931471805599453 / 1024.0;  // ln2 / 1024 (exact scaling of the double ln 2)
+    ex[1] = 1.0 / 2.0;
+    ex[2] = 1.0 / 6.0;
+    ex[3] = 1477.3197218702985;           // 1024 / ln 2
+    ex[4] = ex[5] = ex[6] = 0.0;
 }
 
 int weight_chunks(int64_t N)

@@ -1,10 +1,6 @@
 // wterm.h -- one importance-weight term q_k exp(-|u_j - u_k|^2 / (2 sigma_j^2))
-// with a table-driven exponential (device code shared by the single-run and
-// batched weight kernels).
-//
-// exp: x = (64 k + i) ln2/64 + r with |r| <= ln2/128,
-// exp(x) = 2^k 2^(i/64) (1 + r + r^2/2 + ... + r^5/5!); relative error a few
-// 1e-16.  The constants come in through kernel arguments (scalar registers).
+// with a table-driven exponential, the per-row column loop and the window
+// helpers (device code shared by the single-run and batched weight kernels).
 #pragma once
 
 #include "dmath.h"
@@ -13,35 +9,106 @@
 namespace abcsmc {
 namespace wterm {
 
-constexpr int kTile = 256;  // columns per LDS tile
+constexpr int kTile = 256;  // columns per skip-test tile
 
-__device__ __forceinline__ double exp_tab(double x, const double* T, const double* ex)
+// Scalar-column form used by the weight kernels.  Columns (u_k[8], q_k) are
+// the same for every lane of a wave, so they are read through a wave-uniform
+// pointer in the constant address space (scalar loads into SGPRs, no LDS
+// staging).  The exponential uses a 1024-entry table of 2^(i/1024):
+//   t = D c_j with c_j = -1024 / (2 sigma_j^2 ln 2)  (the exponent in units
+//   of ln2/1024), k = rint(t), r = (t - k) ln2/1024, |r| <= 3.4e-4,
+//   exp = 2^(k >> 10) 2^((k & 1023)/1024) (1 + r + r^2/2 + r^3/6)
+// (truncation r^4/24 < 6e-16 relative).  There is no cut-off: a term with
+// exponent below -708 comes out as 0 or a subnormal-size value, which cannot
+// change a row sum (every row holds its own parent's term, >= e^-185) -- the
+// sums are those of the exact-zero convention.  For t below -2^31 the integer
+// conversion saturates and 2^(k >> 10) underflows to 0.
+constexpr int kTabBits = 10;
+constexpr int kTab = 1 << kTabBits;
+
+typedef const __attribute__((address_space(4))) double* const_col_ptr;  // constant address space
+
+struct Col {
+    double u[kNP];
+    double q;
+};
+
+__device__ __forceinline__ Col load_col(const_col_ptr cols, int k)
 {
-    const double kk = __builtin_rint(x * ex[0]);
-    double r = __builtin_fma(-kk, ex[1], x);
-    r = __builtin_fma(-kk, ex[2], r);
-    const int ik = (int)kk;
-    double p = __builtin_fma(ex[6], r, ex[5]);
-    p = __builtin_fma(p, r, ex[4]);
-    p = __builtin_fma(p, r, ex[3]);
-    p = __builtin_fma(p, r, 1.0);
-    p = __builtin_fma(p, r, 1.0);
-    return __builtin_ldexp(T[ik & 63] * p, ik >> 6);
+    Col c;
+    const_col_ptr p = cols + (size_t)k * 9;
+#pragma unroll
+    for (int d = 0; d < kNP; ++d) c.u[d] = p[d];
+    c.q = p[8];
+    return c;
 }
 
-__device__ __forceinline__ double pair_term(const double* uj, double ninv, const double (*tu)[kTile],
-                                            const double* tq, int c, const double* T, const double* ex)
+// ex[0] = ln2/1024, ex[1] = 1/2, ex[2] = 1/6 (kernel arguments: SGPRs)
+__device__ __forceinline__ double term_c(const double* uj, double cj, const Col& c, const double* T, const double* ex)
 {
     double D = 0.0;
 #pragma unroll
     for (int d = 0; d < kNP; ++d) {
-        const double df = uj[d] - tu[d][c];
+        const double df = uj[d] - c.u[d];
         D = __builtin_fma(df, df, D);
     }
-    const double arg = D * ninv;
-    return arg >= dm::kExpLo ? tq[c] * exp_tab(arg, T, ex) : 0.0;
+    const double t = D * cj;
+    const double kk = __builtin_rint(t);
+    const double r = (t - kk) * ex[0];
+    const int ik = (int)kk;
+    double p = __builtin_fma(r, ex[2], ex[1]);
+    p = __builtin_fma(p, r, 1.0);
+    p = __builtin_fma(p, r, 1.0);
+    return c.q * __builtin_ldexp(T[ik & (kTab - 1)] * p, ik >> kTabBits);
 }
 
+// Per-lane scale c_j of the row's exponent (ex[3] = 1024 / ln 2).
+__device__ __forceinline__ double row_scale(double sigma, const double* ex)
+{
+    return -ex[3] / (2.0 * (sigma * sigma));
+}
+
+// 2^(i/1024), i = 0..1023, into LDS (all threads of the block take part).
+__device__ __forceinline__ void fill_table(double* T)
+{
+    for (int i = threadIdx.x; i < kTab; i += blockDim.x) T[i] = dm::exp((double)i * (0.6931471805599453 / kTab));
+}
+
+// Sum over the sorted columns [k0, k1) for this lane's row, in 256-column
+// tiles; a tile that no row of the wave can reach (sort coordinate outside
+// [wlo, whi]) is skipped.  Two interleaved partial sums, the next pair of
+// columns loaded before the current pair is used.
+__device__ __forceinline__ double row_sum(const double* uj, double cj, const_col_ptr cols, const_col_ptr skey,
+                                          int k0, int k1, double wlo, double whi, const double* T,
+                                          const double* ex, unsigned long long lanes,
+                                          unsigned long long& evaluated)
+{
+    double total = 0.0;
+    for (int c0 = k0; c0 < k1; c0 += kTile) {
+        const int n = min(kTile, k1 - c0);
+        if (skey[c0 + n - 1] < wlo || skey[c0] > whi) continue;
+        evaluated += lanes * (unsigned long long)n;
+        double p0 = 0.0, p1 = 0.0;
+        Col ca = load_col(cols, __builtin_amdgcn_readfirstlane(c0));
+        Col cb = load_col(cols, __builtin_amdgcn_readfirstlane(c0 + (n > 1 ? 1 : 0)));
+        int cc = 0;
+        for (; cc + 1 < n; cc += 2) {
+            const int kn = __builtin_amdgcn_readfirstlane(c0 + (cc + 3 < n ? cc + 2 : cc));
+            const Col na = load_col(cols, kn);
+            const Col nb = load_col(cols, kn + (cc + 3 < n ? 1 : 0));
+            p0 += term_c(uj, cj, ca, T, ex);
+            p1 += term_c(uj, cj, cb, T, ex);
+            ca = na;
+            cb = nb;
+        }
+        if (cc < n) {
+            ca = load_col(cols, __builtin_amdgcn_readfirstlane(c0 + cc));
+            p0 += term_c(uj, cj, ca, T, ex);
+        }
+        total += p0 + p1;
+    }
+    return total;
+}
 
 // Window of a row: a column whose sort coordinate differs by more than
 // kWindow sigma_j gives an exponent below -710, where both exponentials are
@@ -96,9 +163,6 @@ __device__ __forceinline__ double wave_max(double v)
     }
     return v;
 }
-
-// 2^(i/64), i = 0..63, into LDS (call from the first 64 threads).
-__device__ __forceinline__ double table_entry(int i) { return dm::exp((double)i * 0.010830424696249145); }
 
 }  // namespace wterm
 }  // namespace abcsmc

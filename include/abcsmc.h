@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define ABCSMC_ABI_VERSION 1
+#define ABCSMC_ABI_VERSION 2
 #define ABCSMC_NPAR 8
 
 enum {
@@ -53,7 +53,13 @@ enum {
 /* Step-size law of the perturbation kernel. */
 enum {
     ABCSMC_STEP_PAPER = 0, /* eq. 16: s ~ Beta(eps_i / eps_1, 2 i) in stage i >= 1 */
-    ABCSMC_STEP_FIXED = 1  /* s ~ Beta(beta_a, beta_b) in every stage */
+    ABCSMC_STEP_FIXED = 1, /* s ~ Beta(beta_a, beta_b) in every stage */
+    ABCSMC_STEP_MCMC = 2   /* the paper's baseline (§II-D, eqs. 12-15): one step size s for every
+                              proposal of a batch ("run"); after each of the first mcmc_tune batches
+                              of stages >= 1, s <- s (1 + (A - 0.234) / (0.766 (n_acc + 1))) with A =
+                              accepted / valid proposals of the batch and n_acc the acceptances of
+                              all tuned batches so far; needs batch > 0 (whole batches are simulated,
+                              so results depend on it); single-run contexts only */
 };
 
 /* Transition sampler of the simulator (§II-B). */
@@ -94,6 +100,8 @@ typedef struct {
     void* stream;                 /* hipStream_t to run on, or NULL for a library-owned stream */
     void* workspace;              /* optional caller device buffer (e.g. a torch tensor), or NULL */
     size_t workspace_bytes;       /* its size; see abcsmc_workspace_size */
+    double mcmc_s0;               /* STEP_MCMC: initial step size s > 0 */
+    int32_t mcmc_tune;            /* STEP_MCMC: number of tuned batches (>= 0) */
 } abcsmc_config;
 
 typedef struct {
@@ -117,6 +125,7 @@ typedef struct {
     int64_t weight_pairs;         /* N x survivors terms of the importance-weight sums */
     int64_t weight_terms;         /* terms actually evaluated (the rest lie outside every window and
                                      are exactly zero) */
+    double mcmc_s;                /* STEP_MCMC: step size after this stage (0 otherwise) */
 } abcsmc_round_info;
 
 typedef struct abcsmc_ctx abcsmc_ctx;

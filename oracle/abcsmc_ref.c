@@ -308,7 +308,7 @@ typedef struct {
     int32_t n_days;                    /* T */
     int64_t n_particles;               /* N accepted per round */
     double surv_ratio;                 /* alpha of eq. 8 */
-    int32_t step_schedule;             /* 0: eq. 16, 1: fixed Beta(beta_a, beta_b) */
+    int32_t step_schedule;             /* 0: eq. 16, 1: fixed Beta(beta_a, beta_b), 2: MCMC-tuned s (eqs. 12-15) */
     double beta_a;
     int32_t beta_b;
     int32_t step_is_variance;          /* eq. 12 calls s a variance: sigma = sqrt(s) */
@@ -316,6 +316,9 @@ typedef struct {
     int32_t max_attempts;              /* perturbation redraws before a proposal is void */
     uint64_t seed;
     int64_t max_proposals;             /* per-round budget */
+    int64_t batch;                     /* simulations per run (schedule 2: one s per batch) */
+    double mcmc_s0;                    /* schedule 2: initial step size s */
+    int32_t mcmc_tune;                 /* schedule 2: batches of stages >= 1 after which s is adapted */
 } ref_config;
 
 enum { REF_S = 0, REF_I, REF_A, REF_R, REF_D, REF_RU };
@@ -501,7 +504,10 @@ int64_t ref_parent(const uint64_t* C, int64_t n, uint64_t R)
 void ref_beta_shape(const ref_config* cfg, int32_t round, double eps_i, double eps_1,
                     double* a, int32_t* b)
 {
-    if (cfg->step_schedule == 1) {
+    if (cfg->step_schedule == 2) { /* no Beta: the MCMC variant's s is carried separately */
+        *a = 0.0;
+        *b = 0;
+    } else if (cfg->step_schedule == 1) {
         *a = cfg->beta_a;
         *b = cfg->beta_b;
     } else {
@@ -521,12 +527,13 @@ int32_t ref_perturb(const ref_config* cfg, uint32_t round, uint32_t index, const
                     double u_out[REF_NPAR], double* sigma_out, int64_t* parent_out)
 {
     uint64_t words[5 + 128];
+    const int fixed_s = cfg->step_schedule == 2; /* MCMC variant: s = beta_a, no Beta words */
     for (int32_t att = 0; att < cfg->max_attempts; ++att) {
-        int nw = 5 + beta_b;
+        int nw = 5 + (fixed_s ? 0 : beta_b);
         for (int k = 0; k < nw; ++k)
             words[k] = ref_word(cfg->seed, index, round, REF_PERTURB, (uint32_t)att, (uint32_t)k);
         int64_t parent = ref_parent(C, n_prev, words[0]);
-        double s = ref_beta_int(beta_a, beta_b, words + 5);
+        double s = fixed_s ? beta_a : ref_beta_int(beta_a, beta_b, words + 5);
         double sigma = cfg->step_is_variance ? sqrt(s) : s;
         if (sigma < 1e-8) sigma = 1e-8;
         double z[REF_NPAR];
@@ -617,6 +624,21 @@ double ref_normalise(const double* l, int64_t n, double* W)
 }
 
 /* ------------------------------------------------------------------ */
+/* MCMC variant (§II-D, eqs. 12-15): after a batch ("run") of proposals
+ * with acc of its valid proposals accepted (eq. 14, A = acc / valid), the
+ * step size moves toward the target acceptance A_T = 0.234 by
+ *   s_new = s_old (1 + (A - A_T) / ((1 - A_T) (n_acc + 1)))
+ * where n_acc counts every acceptance of the tuned batches so far, this one
+ * included.  (Eq. 15 as printed multiplies s by (A - A_T) itself, which turns
+ * s negative whenever A < A_T; the relative-change reading keeps its sign
+ * and its 1 / (n_acc + 1) gain.) */
+double ref_mcmc_update(double s, int64_t acc, int64_t valid, int64_t n_acc)
+{
+    const double A_T = 0.234;
+    const double A = valid > 0 ? (double)acc / (double)valid : 0.0;
+    return s * (1.0 + (A - A_T) / ((1.0 - A_T) * ((double)n_acc + 1.0)));
+}
+
 /* Whole run: stage 0 (ABC with eps^0 = +inf, §II-D) then stages        */
 /* 1..R-1 (eqs. 8-11, 16-17).                                           */
 /* ------------------------------------------------------------------ */
@@ -638,6 +660,8 @@ typedef struct {
     int64_t* invalid;   /* void proposals among them */
     int64_t* attempts_total;
     double* ess;
+    double* mcmc_s;   /* schedule 2: step size after stage r (its starting value for stage 0) */
+    int64_t* simulated; /* proposals simulated: whole batches for schedule 2, else = proposals */
 } ref_result;
 
 /* Returns 0 on success, -4 if a round exhausted max_proposals (result
@@ -652,6 +676,9 @@ int ref_run(const ref_config* cfg, const int64_t* obs, int32_t n_rounds, ref_res
     uint64_t* C = (uint64_t*)malloc((size_t)N * sizeof(uint64_t));
     int rc = 0;
     double eps1 = INFINITY;
+    double s_mcmc = cfg->mcmc_s0;  /* schedule 2 state, carried across stages */
+    int32_t tunes = 0;
+    int64_t n_acc = 0;
     for (int32_t r = 0; r < n_rounds; ++r) {
         double* u = out->u + (size_t)r * N * REF_NPAR;
         double* dist = out->dist + (size_t)r * N;
@@ -687,27 +714,72 @@ int ref_run(const ref_config* cfg, const int64_t* obs, int32_t n_rounds, ref_res
             out->beta_a[r] = ba;
             out->beta_b[r] = bb;
             ref_resample_weights(d_prev, N, eps, q, C);
-            while (accepted < N) {
-                if (j >= cfg->max_proposals) { rc = -4; break; }
-                double uj[REF_NPAR], s; int64_t parent;
-                int32_t a = ref_perturb(cfg, (uint32_t)r, (uint32_t)j, u_prev, C, N, ba, bb, uj, &s, &parent);
-                att_total += a > 0 ? a : -a;
-                if (a < 0) { ++invalid; ++j; continue; }
-                double d = ref_sim_distance(cfg, obs, uj, (uint32_t)r, (uint32_t)j, traj);
-                if (d <= eps) { /* accept: dist <= eps (§II-C) */
-                    memcpy(u + (size_t)accepted * REF_NPAR, uj, sizeof uj);
-                    dist[accepted] = d; sig[accepted] = s; par[accepted] = parent;
-                    idx[accepted] = j; att[accepted] = a;
-                    ++accepted;
+            if (cfg->step_schedule != 2) {
+                while (accepted < N) {
+                    if (j >= cfg->max_proposals) { rc = -4; break; }
+                    double uj[REF_NPAR], s; int64_t parent;
+                    int32_t a = ref_perturb(cfg, (uint32_t)r, (uint32_t)j, u_prev, C, N, ba, bb, uj, &s, &parent);
+                    att_total += a > 0 ? a : -a;
+                    if (a < 0) { ++invalid; ++j; continue; }
+                    double d = ref_sim_distance(cfg, obs, uj, (uint32_t)r, (uint32_t)j, traj);
+                    if (d <= eps) { /* accept: dist <= eps (§II-C) */
+                        memcpy(u + (size_t)accepted * REF_NPAR, uj, sizeof uj);
+                        dist[accepted] = d; sig[accepted] = s; par[accepted] = parent;
+                        idx[accepted] = j; att[accepted] = a;
+                        ++accepted;
+                    }
+                    ++j;
                 }
-                ++j;
+                out->simulated[r] = j;
+            } else {
+                /* MCMC variant: batches of cfg->batch proposals, one s per batch;
+                 * a batch is simulated whole, acceptances past the N-th are
+                 * counted for eq. 14 but not kept */
+                int64_t base = 0, proposals = -1, inval_all = 0, att_all = 0;
+                while (accepted < N) {
+                    if (base >= cfg->max_proposals) { rc = -4; break; }
+                    int64_t B = cfg->batch;
+                    if (base + B > cfg->max_proposals) B = cfg->max_proposals - base;
+                    int64_t acc_b = 0, valid_b = 0;
+                    for (j = base; j < base + B; ++j) {
+                        double uj[REF_NPAR], s; int64_t parent;
+                        int32_t a = ref_perturb(cfg, (uint32_t)r, (uint32_t)j, u_prev, C, N, s_mcmc, 0, uj, &s,
+                                                &parent);
+                        att_all += a > 0 ? a : -a;
+                        if (a < 0) { ++inval_all; continue; }
+                        ++valid_b;
+                        double d = ref_sim_distance(cfg, obs, uj, (uint32_t)r, (uint32_t)j, traj);
+                        if (d <= eps) {
+                            ++acc_b;
+                            if (accepted < N) {
+                                memcpy(u + (size_t)accepted * REF_NPAR, uj, sizeof uj);
+                                dist[accepted] = d; sig[accepted] = s; par[accepted] = parent;
+                                idx[accepted] = j; att[accepted] = a;
+                                ++accepted;
+                                if (accepted == N) proposals = j + 1;
+                            }
+                        }
+                    }
+                    base += B;
+                    if (tunes < cfg->mcmc_tune) {
+                        n_acc += acc_b;
+                        s_mcmc = ref_mcmc_update(s_mcmc, acc_b, valid_b, n_acc);
+                        ++tunes;
+                    }
+                }
+                if (rc != 0) break;
+                j = proposals;
+                invalid = inval_all;
+                att_total = att_all;
+                out->simulated[r] = base;
             }
             if (rc != 0) break;
             for (int64_t k = 0; k < N; ++k)
                 lw[k] = ref_log_weight(u + (size_t)k * REF_NPAR, sig[k], u_prev, q, N);
             out->ess[r] = ref_normalise(lw, N, W);
         }
-        if (r == 0) out->ess[0] = (double)N;
+        if (r == 0) { out->ess[0] = (double)N; out->simulated[0] = N; }
+        out->mcmc_s[r] = s_mcmc;
         out->proposals[r] = j;
         out->invalid[r] = invalid;
         out->attempts_total[r] = att_total;

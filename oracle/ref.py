@@ -39,6 +39,7 @@ class Config(C.Structure):
         ("surv_ratio", C.c_double), ("step_schedule", C.c_int32), ("beta_a", C.c_double),
         ("beta_b", C.c_int32), ("step_is_variance", C.c_int32), ("sampler", C.c_int32),
         ("max_attempts", C.c_int32), ("seed", C.c_uint64), ("max_proposals", C.c_int64),
+        ("batch", C.c_int64), ("mcmc_s0", C.c_double), ("mcmc_tune", C.c_int32),
     ]
 
 
@@ -48,7 +49,7 @@ class Result(C.Structure):
         ("index", C.c_void_p), ("attempts", C.c_void_p), ("logw", C.c_void_p), ("W", C.c_void_p),
         ("eps", C.c_void_p), ("eps_next", C.c_void_p), ("beta_a", C.c_void_p), ("beta_b", C.c_void_p),
         ("proposals", C.c_void_p), ("invalid", C.c_void_p), ("attempts_total", C.c_void_p),
-        ("ess", C.c_void_p),
+        ("ess", C.c_void_p), ("mcmc_s", C.c_void_p), ("simulated", C.c_void_p),
     ]
 
 
@@ -85,6 +86,7 @@ def lib():
             "ref_log_weight": (d, [vp, d, vp, vp, i64]),
             "ref_normalise": (d, [vp, i64, vp]),
             "ref_run": (i32, [vp, vp, i32, vp]),
+            "ref_mcmc_update": (d, [d, i64, i64, i64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -116,6 +118,9 @@ def make_config(w, **over) -> Config:
     c.max_attempts = w.max_attempts
     c.seed = w.seed
     c.max_proposals = w.max_proposals or 4096 * w.n_particles
+    c.batch = w.batch
+    c.mcmc_s0 = w.mcmc_s0
+    c.mcmc_tune = w.mcmc_tune
     return c
 
 
@@ -237,6 +242,11 @@ def sim_distance(w, obs, u, rnd: int, index: int, **over) -> float:
     return lib().ref_sim_distance(C.byref(cfg), _p(obs), _p(u), rnd, index, _p(traj))
 
 
+def mcmc_update(s: float, acc: int, valid: int, n_acc: int) -> float:
+    """Step size after a tuned batch of the MCMC variant (eqs. 14-15 reading)."""
+    return lib().ref_mcmc_update(s, acc, valid, n_acc)
+
+
 def perturb(w, rnd: int, index: int, u_prev, Cc, beta_a: float, beta_b: int, **over):
     """Returns (attempts, u, sigma, parent); attempts < 0 marks a void proposal."""
     cfg = make_config(w, **over)
@@ -269,6 +279,8 @@ class RunResult:
     invalid: np.ndarray
     attempts_total: np.ndarray
     ess: np.ndarray
+    mcmc_s: np.ndarray
+    simulated: np.ndarray
 
     def theta(self, w) -> np.ndarray:
         lo = np.asarray(w.lo)
@@ -287,7 +299,8 @@ def run(w, obs, n_rounds: Optional[int] = None, **over) -> RunResult:
         attempts=np.zeros((R, N), np.int32), logw=np.zeros((R, N)), W=np.zeros((R, N)),
         eps=np.zeros(R), eps_next=np.zeros(R), beta_a=np.zeros(R), beta_b=np.zeros(R, np.int32),
         proposals=np.zeros(R, np.int64), invalid=np.zeros(R, np.int64),
-        attempts_total=np.zeros(R, np.int64), ess=np.zeros(R),
+        attempts_total=np.zeros(R, np.int64), ess=np.zeros(R), mcmc_s=np.zeros(R),
+        simulated=np.zeros(R, np.int64),
     )
     res = Result(**{k: v.ctypes.data for k, v in arrs.items()})
     obs = np.ascontiguousarray(obs, dtype=np.int64)

@@ -20,7 +20,7 @@ from . import workloads as W
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libabcsmc_hip.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 OK, EINVAL, ENOMEM, EDEVICE, EBUDGET, ESTATE, EDEGENERATE = 0, -1, -2, -3, -4, -5, -6
 F_EARLY_EXIT = 1
 F_STEP_IS_VARIANCE = 2
@@ -55,7 +55,7 @@ class Config(C.Structure):
         ("beta_a", C.c_double), ("beta_b", C.c_int32), ("sampler", C.c_int32),
         ("flags", C.c_int32), ("max_attempts", C.c_int32), ("seed", C.c_uint64),
         ("max_proposals", C.c_int64), ("stream", C.c_void_p), ("workspace", C.c_void_p),
-        ("workspace_bytes", C.c_size_t),
+        ("workspace_bytes", C.c_size_t), ("mcmc_s0", C.c_double), ("mcmc_tune", C.c_int32),
     ]
 
 
@@ -76,7 +76,7 @@ class RoundInfo(C.Structure):
         ("ms_simulate", C.c_double), ("ms_weights", C.c_double), ("ms_select", C.c_double),
         ("ms_total", C.c_double), ("ms_k_propose", C.c_double), ("ms_k_weights", C.c_double),
         ("n_k_propose", C.c_int64), ("sim_days", C.c_int64), ("weight_pairs", C.c_int64),
-        ("weight_terms", C.c_int64),
+        ("weight_terms", C.c_int64), ("mcmc_s", C.c_double),
     ]
 
     def as_dict(self):
@@ -207,6 +207,8 @@ def make_config(w: W.Workload, *, stream=None, workspace=None, flags: int = 0, *
     c.max_attempts = w.max_attempts
     c.seed = w.seed
     c.max_proposals = w.max_proposals
+    c.mcmc_s0 = w.mcmc_s0
+    c.mcmc_tune = w.mcmc_tune
     c.stream = stream
     if workspace is not None:
         ptr, nbytes = workspace

@@ -100,6 +100,9 @@ struct abcsmc_ctx {
     double eps_next = INFINITY;  // eps of the next stage
     double eps1 = INFINITY;      // eps of stage 1 (eq. 16 normaliser)
     double last_rate = 0.5;      // acceptance rate of the last stage (batch sizing)
+    double mcmc_s = 0.0;         // MCMC variant: current step size
+    int32_t mcmc_tunes = 0;      // MCMC variant: tuned batches so far
+    int64_t mcmc_nacc = 0;       // MCMC variant: acceptances of the tuned batches
     int64_t N = 0;
     template <typename T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }

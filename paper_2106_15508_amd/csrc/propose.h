@@ -149,6 +149,7 @@ struct ProposalIn {
     double beta_a;
     int32_t beta_b;
     int32_t step_is_variance;
+    double s_fixed;          // >= 0: step size of every proposal (MCMC variant); < 0: Beta draw
 };
 
 struct ProposalOut {
@@ -200,7 +201,8 @@ __device__ __forceinline__ void perturb_one(const Model& m, const ProposalIn& a,
                 // Beta(a, b), b integer: exp( sum_m log U_m / (a + m) )
                 double L = 0.0;
                 uint64_t hold = 0;
-                for (int32_t mm = 0; mm < a.beta_b; ++mm) {
+                const int32_t nb = a.s_fixed >= 0.0 ? 0 : a.beta_b;
+                for (int32_t mm = 0; mm < nb; ++mm) {
                     uint64_t w;
                     if (mm == 0) {
                         w = b2.b;
@@ -214,7 +216,7 @@ __device__ __forceinline__ void perturb_one(const Model& m, const ProposalIn& a,
                     }
                     L = L + dm::log(dm::u01(w)) / (a.beta_a + (double)mm);
                 }
-                const double s = dm::exp(L);
+                const double s = a.s_fixed >= 0.0 ? a.s_fixed : dm::exp(L);
                 double sg = a.step_is_variance ? __builtin_sqrt(s) : s;
                 if (sg < 1e-8) sg = 1e-8;
                 double z[kNP];

@@ -101,8 +101,12 @@ int validate(const abcsmc_config* c, const int64_t* obs, std::string* err)
     if (c->n_particles < 2 || c->n_particles > ((int64_t)1 << 22)) return fail(err, ABCSMC_EINVAL, "n_particles must be in [2, 2^22]");
     if (c->batch < 0 || c->batch > ((int64_t)1 << 24)) return fail(err, ABCSMC_EINVAL, "batch must be in [0, 2^24]");
     if (!(c->surv_ratio > 0.0 && c->surv_ratio < 1.0)) return fail(err, ABCSMC_EINVAL, "surv_ratio must be in (0,1)");
-    if (c->step_schedule != ABCSMC_STEP_PAPER && c->step_schedule != ABCSMC_STEP_FIXED)
+    if (c->step_schedule != ABCSMC_STEP_PAPER && c->step_schedule != ABCSMC_STEP_FIXED &&
+        c->step_schedule != ABCSMC_STEP_MCMC)
         return fail(err, ABCSMC_EINVAL, "unknown step_schedule");
+    if (c->step_schedule == ABCSMC_STEP_MCMC &&
+        (c->batch <= 0 || !(c->mcmc_s0 > 0.0) || !std::isfinite(c->mcmc_s0) || c->mcmc_tune < 0))
+        return fail(err, ABCSMC_EINVAL, "MCMC step schedule needs batch > 0, mcmc_s0 > 0 and mcmc_tune >= 0");
     if (c->step_schedule == ABCSMC_STEP_FIXED && (!(c->beta_a > 0.0) || !std::isfinite(c->beta_a) || c->beta_b < 1 || c->beta_b > 64))
         return fail(err, ABCSMC_EINVAL, "fixed Beta needs a > 0 and integer 1 <= b <= 64");
     if (c->sampler != ABCSMC_SAMPLER_BINOMIAL && c->sampler != ABCSMC_SAMPLER_NORMAL_FLOOR)
@@ -219,6 +223,7 @@ int abcsmc_init(const abcsmc_config* cfg, const int64_t* obs, abcsmc_ctx** out)
     if (x->cfg.max_proposals == 0 || x->cfg.max_proposals > cap)
         x->cfg.max_proposals = std::min<int64_t>(cap, x->cfg.max_proposals ? x->cfg.max_proposals : 4096 * x->N);
     x->obs.assign(obs, obs + (size_t)(cfg->n_days + 1) * 3);
+    x->mcmc_s = cfg->mcmc_s0;
     x->model = make_model(x->cfg, obs);
     x->L = make_layout(x->cfg);
     auto bail = [&](int code) {
@@ -283,6 +288,9 @@ int abcsmc_reset(abcsmc_ctx* x)
     x->eps_next = INFINITY;
     x->eps1 = INFINITY;
     x->last_rate = 0.5;
+    x->mcmc_s = x->cfg.mcmc_s0;
+    x->mcmc_tunes = 0;
+    x->mcmc_nacc = 0;
     if (x->sur) return surrogate_reset(x);
     return ABCSMC_OK;
 }
@@ -304,7 +312,7 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
     const double eps = r == 0 ? INFINITY : x->eps_next;
     double ba = 0.0;
     int32_t bb = 0;
-    if (r > 0) {
+    if (r > 0 && c.step_schedule != ABCSMC_STEP_MCMC) {
         if (c.step_schedule == ABCSMC_STEP_FIXED) {
             ba = c.beta_a;
             bb = c.beta_b;
@@ -347,6 +355,8 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
     pa.beta_a = ba;
     pa.beta_b = bb;
     pa.step_is_variance = (c.flags & ABCSMC_F_STEP_IS_VARIANCE) ? 1 : 0;
+    const bool mcmc = c.step_schedule == ABCSMC_STEP_MCMC;
+    pa.s_fixed = (mcmc && r > 0) ? x->mcmc_s : -1.0;
     pa.st_u = x->at<double>(x->L.st_u);
     pa.st_d = x->at<double>(x->L.st_d);
     pa.st_sigma = x->at<double>(x->L.st_sigma);
@@ -370,6 +380,7 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
     int64_t base = 0, batches = 0;
     double ms_k_propose = 0.0;
     StageCounters hc{};
+    unsigned long long prev_acc = 0, prev_inv = 0;
     if (screened) {
         const int rc = surrogate_batches(x, pa, dst, nxt, hc, base, batches, ms_k_propose);
         if (rc) return rc;
@@ -404,6 +415,18 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
         ms_k_propose += elapsed(x->ev[5], x->ev[6]);
         base += B;
         ++batches;
+        if (mcmc && r > 0 && x->mcmc_tunes < c.mcmc_tune) {
+            // eqs. 14-15 over this batch: A = accepted / valid proposals
+            const int64_t acc_b = (int64_t)(hc.accepted - prev_acc);
+            const int64_t valid_b = B - (int64_t)(hc.invalid - prev_inv);
+            x->mcmc_nacc += acc_b;
+            const double A = valid_b > 0 ? (double)acc_b / (double)valid_b : 0.0;
+            x->mcmc_s = x->mcmc_s * (1.0 + (A - 0.234) / ((1.0 - 0.234) * ((double)x->mcmc_nacc + 1.0)));
+            x->mcmc_tunes += 1;
+            pa.s_fixed = x->mcmc_s;
+        }
+        prev_acc = hc.accepted;
+        prev_inv = hc.invalid;
         if (hc.accepted >= (unsigned long long)N) break;
         if (r > 0 && base > 0) x->last_rate = (double)hc.accepted / (double)base;
     }
@@ -490,6 +513,7 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
         I.sim_days = (int64_t)hc.days;
         I.weight_pairs = r == 0 ? 0 : (int64_t)N * (int64_t)hc.survivors;
         I.weight_terms = (int64_t)hterms;
+        I.mcmc_s = mcmc ? x->mcmc_s : 0.0;
     }
     return ABCSMC_OK;
 }

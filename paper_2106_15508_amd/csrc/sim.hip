@@ -28,7 +28,7 @@ void propose_kernel(ProposeArgs a)
     const bool active = p < a.count;
     const uint32_t j = a.base + p;
     const lane::ProposalIn in{a.obs,    a.round,  a.max_attempts, a.eps,   a.exit_thr,          a.u_prev,
-                              a.cdf,    a.n_prev, a.beta_a,       a.beta_b, a.step_is_variance};
+                              a.cdf,    a.n_prev, a.beta_a,       a.beta_b, a.step_is_variance, a.s_fixed};
     lane::ProposalOut o;
     o.valid = false;
     o.acc = false;

@@ -455,6 +455,8 @@ int abcsmc_surrogate_enable(abcsmc_ctx* x, const abcsmc_surrogate_config* scfg)
 {
     if (!x) return fail(nullptr, ABCSMC_EINVAL, "ctx is NULL");
     if (x->broken) return fail(&x->err, ABCSMC_ESTATE, "context unusable after a device error");
+    if (x->cfg.step_schedule == ABCSMC_STEP_MCMC)
+        return fail(&x->err, ABCSMC_EINVAL, "the surrogate screen needs a Beta step schedule");
     abcsmc_surrogate_config def{};
     const abcsmc_surrogate_config c = with_defaults(scfg ? scfg : &def);
     int rc = check_scfg(c, &x->err);

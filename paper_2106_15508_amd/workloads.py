@@ -41,6 +41,7 @@ OBS_ROUND = 0xFFFF
 
 STEP_PAPER = 0   # eq. (16): Beta(eps_i / eps_1, 2 i)
 STEP_FIXED = 1   # Beta(beta_a, beta_b) in every round
+STEP_MCMC = 2    # one MCMC-tuned step size s per batch (eqs. 12-15); batch > 0
 SAMPLER_BINOMIAL = 0
 SAMPLER_NORMAL_FLOOR = 1
 
@@ -66,6 +67,8 @@ class Workload:
     batch: int = 0            # proposals per batch, 0 = library default
     max_proposals: int = 0    # per-round budget, 0 = 4096 * N
     theta_true: Sequence[float] = THETA_TRUE
+    mcmc_s0: float = 0.1      # STEP_MCMC: initial step size
+    mcmc_tune: int = 100      # STEP_MCMC: tuned batches (the first 10% of a 1000-run budget)
 
     @property
     def a0(self) -> int:

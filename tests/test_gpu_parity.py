@@ -174,3 +174,23 @@ def test_weights_before_round_is_state_error(oracle):
         with pytest.raises(A.AbcsmcError) as e:
             ctx.weights()
         assert e.value.code == A.ESTATE
+
+
+@pytest.mark.parametrize("wl", [
+    W.tiny(step_schedule=W.STEP_MCMC, batch=256, mcmc_s0=0.1, mcmc_tune=5),
+    W.tiny(step_schedule=W.STEP_MCMC, batch=1000, mcmc_s0=0.003, mcmc_tune=100, step_is_variance=True, seed=5),
+    W.C1.with_(step_schedule=W.STEP_MCMC, batch=1024, mcmc_s0=0.05, mcmc_tune=3),
+])
+def test_mcmc_variant_bitwise(oracle, wl):
+    """The paper's baseline (one tuned step size per batch, eqs. 12-15):
+    every stage, the step size after every tuned batch and the whole-batch
+    counts agree with the oracle bit for bit."""
+    obs = oracle.observations(wl)
+    ref = oracle.run(wl, obs)
+    assert ref.rc == 0
+    infos, pops = _gpu_run(wl, obs, wl.n_rounds, flags=A.F_EARLY_EXIT)
+    _compare_run(oracle, wl, ref, infos, pops, wl.n_rounds)
+    for i in range(1, wl.n_rounds):
+        assert _bits([infos[i]["mcmc_s"]])[0] == _bits([ref.mcmc_s[i]])[0], i
+        assert infos[i]["simulated"] == ref.simulated[i], i
+        assert infos[i]["invalid"] == ref.invalid[i], i

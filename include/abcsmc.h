@@ -160,6 +160,18 @@ int abcsmc_population(const abcsmc_ctx* ctx, double* u, double* sigma, int64_t* 
  * ABCSMC_ESTATE before stage 1. */
 int abcsmc_resampling(const abcsmc_ctx* ctx, uint64_t* q, uint64_t* cdf);
 
+/* Posterior predictive simulation (§IV-B, Fig. 7): every particle j of the
+ * last completed stage (theta_j = lo + u_j (hi - lo)) is simulated for
+ * n_days days from the observed day-0 state with the random stream (seed,
+ * particle j, round 0xFFFE); for each day t = 0..n_days and series c = A, R,
+ * D the type-7 quantiles (numpy "linear") of the N simulated counts at the
+ * n_quant levels quant[] (in [0, 1], 1 <= n_quant <= 64) are written to
+ * bands[(3 t + c) n_quant + k].  n_days may exceed the fitted horizon (the
+ * days after it are the prediction).  Allocates (n_days+1) x 3 x N doubles of
+ * device memory for the duration of the call (ABCSMC_ENOMEM if it cannot). */
+int abcsmc_predict(const abcsmc_ctx* ctx, int32_t n_days, uint64_t seed, int32_t n_quant, const double* quant,
+                   double* bands);
+
 /* Restart the context at stage 0 with the same configuration and seed
  * (the workspace and observations stay resident).  The next abcsmc_round
  * repeats the run bit for bit. */

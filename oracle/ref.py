@@ -242,6 +242,28 @@ def sim_distance(w, obs, u, rnd: int, index: int, **over) -> float:
     return lib().ref_sim_distance(C.byref(cfg), _p(obs), _p(u), rnd, index, _p(traj))
 
 
+PREDICT_ROUND = 0xFFFE
+
+
+def predict(w, obs, u_pop, n_days: int, seed: int, quantiles) -> np.ndarray:
+    """Posterior predictive bands (§IV-B): each particle simulated for n_days
+    from the observed day-0 state with stream (seed, j, PREDICT_ROUND); per
+    day and series (A, R, D) the type-7 quantiles over the particles."""
+    wp = w.with_(n_days=n_days)
+    lo, hi = np.asarray(w.lo), np.asarray(w.hi)
+    series = np.zeros((n_days + 1, 3, len(u_pop)))
+    for j, u in enumerate(u_pop):
+        theta = lo + u * (hi - lo)
+        traj = simulate(wp, theta, seed, PREDICT_ROUND, j, obs0=obs[0])
+        series[:, :, j] = traj[:, 2:5]
+    out = np.zeros((n_days + 1, 3, len(quantiles)))
+    for t in range(n_days + 1):
+        for c in range(3):
+            for k, a in enumerate(quantiles):
+                out[t, c, k] = quantile(series[t, c], a)
+    return out
+
+
 def mcmc_update(s: float, acc: int, valid: int, n_acc: int) -> float:
     """Step size after a tuned batch of the MCMC variant (eqs. 14-15 reading)."""
     return lib().ref_mcmc_update(s, acc, valid, n_acc)

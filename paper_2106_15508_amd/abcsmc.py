@@ -36,7 +36,7 @@ EXPORTS = (
     "abcsmc_batch_free", "abcsmc_batch_last_error",
     "abcsmc_surrogate_enable", "abcsmc_surrogate_disable", "abcsmc_surrogate_info_get", "abcsmc_surrogate_params",
     "abcsmc_surrogate_data", "abcsmc_surrogate_audit", "abcsmc_mlp_param_count", "abcsmc_mlp_init",
-    "abcsmc_mlp_forward", "abcsmc_mlp_gradients", "abcsmc_mlp_train",
+    "abcsmc_mlp_forward", "abcsmc_mlp_gradients", "abcsmc_mlp_train", "abcsmc_predict",
 )
 
 
@@ -164,6 +164,7 @@ def load(path: Optional[str] = None):
         "abcsmc_mlp_forward": (C.c_int, [vp, i64, vp, vp]),
         "abcsmc_mlp_gradients": (C.c_int, [vp, i64, vp, vp, vp, vp]),
         "abcsmc_mlp_train": (C.c_int, [vp, i64, vp, vp, i32, i32, d, vp]),
+        "abcsmc_predict": (C.c_int, [vp, i32, u64, i32, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -301,6 +302,13 @@ class Context:
         q, cdf = np.zeros(N, np.uint64), np.zeros(N, np.uint64)
         _check(self.L.abcsmc_resampling(self._h, _p(q), _p(cdf)), self._h)
         return q, cdf
+
+    def predict(self, n_days: int, seed: int, quantiles=(0.005, 0.5, 0.995)) -> np.ndarray:
+        """abcsmc_predict: (n_days+1) x 3 (A, R, D) x len(quantiles) bands."""
+        q = np.ascontiguousarray(quantiles, dtype=np.float64)
+        out = np.zeros((n_days + 1, 3, q.size))
+        _check(self.L.abcsmc_predict(self._h, n_days, seed, q.size, _p(q), _p(out)), self._h)
+        return out
 
     # -- learned surrogate screen
     def surrogate_enable(self, **kw) -> dict:

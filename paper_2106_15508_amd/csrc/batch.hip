@@ -9,6 +9,7 @@
 // gives the same bits batched or alone; only the weights' summation order
 // differs (1e-12).
 #include "batch.h"
+#include "blockselect.h"
 #include "dmath.h"
 #include "propose.h"
 #include "wterm.h"
@@ -55,21 +56,7 @@ __device__ __forceinline__ double bmax(double v, double* sh)
     return r;
 }
 
-__device__ __forceinline__ unsigned long long bscan_excl(unsigned long long v, unsigned long long* sh)
-{
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-        const unsigned long long x = t >= off ? sh[t - off] : 0ull;
-        __syncthreads();
-        sh[t] += x;
-        __syncthreads();
-    }
-    const unsigned long long r = sh[t] - v;
-    __syncthreads();
-    return r;
-}
+using bsel::bscan_excl;
 
 // ------------------------------------------------------------------ begin/end
 
@@ -677,75 +664,12 @@ __global__ __launch_bounds__(kBlock) void bnormalise_kernel(BatchArgs a, int uni
 // digits and interpolation as the single-run kernels).
 __global__ __launch_bounds__(kBlock) void bselect_kernel(BatchArgs a)
 {
-    constexpr int kBins = 2048;
-    __shared__ unsigned int h[2][kBins];
-    __shared__ unsigned long long part[kBlock];
-    __shared__ unsigned long long st[8];
+    __shared__ bsel::Shared sh;
     const BRun& R = a.runs[blockIdx.x];
     BState& S = a.st[blockIdx.x];
-    if (S.failed) return;
-    const double* x = R.d[S.nxt];
-    const int N = R.N;
-    const double v = ((double)N - 1.0) * R.surv_ratio;
-    long long r0, r1;
-    if (v >= (double)N - 1.0) {
-        r0 = r1 = N - 1;
-    } else if (v < 0.0) {
-        r0 = r1 = 0;
-    } else {
-        r0 = (long long)__builtin_floor(v);
-        r1 = r0 + 1;
-    }
-    if (threadIdx.x == 0) {
-        st[0] = st[1] = st[2] = st[3] = 0ull;  // prefixes, masks
-        st[4] = (unsigned long long)r0;
-        st[5] = (unsigned long long)r1;
-    }
-    for (int pass = 0; pass < 6; ++pass) {
-        for (int b = threadIdx.x; b < 2 * kBins; b += kBlock) (&h[0][0])[b] = 0u;
-        __syncthreads();
-        const int sh = pass < 5 ? 53 - 11 * pass : 0;
-        const unsigned long long dmk = (1ull << (pass < 5 ? 11 : 9)) - 1ull;
-        const unsigned long long p0 = st[0], p1 = st[1], m0 = st[2], m1 = st[3];
-        for (int k = threadIdx.x; k < N; k += kBlock) {
-            const unsigned long long bits = (unsigned long long)__double_as_longlong(x[k]);
-            const unsigned int dig = (unsigned int)((bits >> sh) & dmk);
-            if ((bits & m0) == p0) atomicAdd(&h[0][dig], 1u);
-            if ((bits & m1) == p1) atomicAdd(&h[1][dig], 1u);
-        }
-        __syncthreads();
-        const int nb = (int)dmk + 1;
-        const int per = (nb + kBlock - 1) / kBlock;
-        for (int which = 0; which < 2; ++which) {
-            const unsigned long long rank = st[4 + which];
-            const int b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
-            unsigned long long s = 0;
-            for (int b = b0; b < b1; ++b) s += h[which][b];
-            unsigned long long run = bscan_excl(s, part);
-            for (int b = b0; b < b1; ++b) {
-                if (run <= rank && rank < run + h[which][b]) {
-                    st[4 + which] = rank - run;
-                    st[which] |= (unsigned long long)b << sh;
-                    st[2 + which] |= dmk << sh;
-                }
-                run += h[which][b];
-            }
-            __syncthreads();
-        }
-    }
-    if (threadIdx.x == 0) {
-        const double xa = __longlong_as_double((long long)st[0]);
-        const double xb = __longlong_as_double((long long)st[1]);
-        double res;
-        if (r0 == r1) {
-            res = xa;
-        } else {
-            const double g = v - __builtin_floor(v);
-            const double diff = xb - xa;
-            res = g >= 0.5 ? xb - diff * (1.0 - g) : xa + diff * g;
-        }
-        S.eps_next = res;
-    }
+    if (S.failed) return;  // uniform across the block
+    const double res = bsel::quantile7(R.d[S.nxt], R.N, 1, R.surv_ratio, sh);
+    if (threadIdx.x == 0) S.eps_next = res;
 }
 
 }  // namespace

@@ -24,11 +24,14 @@ namespace lane {
 // With kSplit the three series' sums of squares also go to split[0..2]
 // (no early exit; the surrogate's training targets); the returned distance
 // is the same as without.
+// With kTraj and series != null the trajectory's (A, R, D) go to
+// series[(3 t + c) * sstride] (day t = 0..T) instead of traj.
 template <int kSampler, bool kTraj, bool kSplit = false>
 __device__ __forceinline__ double simulate_distance(const Model& m, const double* th,
                                                     const double* __restrict__ obs, uint32_t round,
                                                     uint32_t index, double exit_thr, int64_t* traj,
-                                                    int32_t& days, double* split = nullptr)
+                                                    int32_t& days, double* split = nullptr,
+                                                    double* series = nullptr, int64_t sstride = 0)
 {
     const double alpha0 = th[0], alpha_c = th[1], n_exp = th[2], beta = th[3];
     const double gamma = th[4], delta = th[5], eta = th[6], kappa = th[7];
@@ -47,8 +50,14 @@ __device__ __forceinline__ double simulate_distance(const Model& m, const double
         pIRu = -dm::expm1(-(beta * eta));
     }
     if (kTraj) {
-        traj[0] = (int64_t)S; traj[1] = (int64_t)I; traj[2] = (int64_t)A;
-        traj[3] = (int64_t)R; traj[4] = (int64_t)D; traj[5] = (int64_t)Ru;
+        if (series) {
+            series[0] = A;
+            series[sstride] = R;
+            series[2 * sstride] = D;
+        } else {
+            traj[0] = (int64_t)S; traj[1] = (int64_t)I; traj[2] = (int64_t)A;
+            traj[3] = (int64_t)R; traj[4] = (int64_t)D; traj[5] = (int64_t)Ru;
+        }
     }
     double acc = 0.0;
     for (int32_t t = 0; t < m.T; ++t) {
@@ -83,9 +92,16 @@ __device__ __forceinline__ double simulate_distance(const Model& m, const double
         D = D + n4;
         Ru = Ru + n5;
         if (kTraj) {
-            int64_t* row = traj + (size_t)(t + 1) * 6;
-            row[0] = (int64_t)S; row[1] = (int64_t)I; row[2] = (int64_t)A;
-            row[3] = (int64_t)R; row[4] = (int64_t)D; row[5] = (int64_t)Ru;
+            if (series) {
+                double* col = series + (size_t)(3 * (t + 1)) * sstride;
+                col[0] = A;
+                col[sstride] = R;
+                col[2 * sstride] = D;
+            } else {
+                int64_t* row = traj + (size_t)(t + 1) * 6;
+                row[0] = (int64_t)S; row[1] = (int64_t)I; row[2] = (int64_t)A;
+                row[3] = (int64_t)R; row[4] = (int64_t)D; row[5] = (int64_t)Ru;
+            }
         }
         if (kSplit) {
             const double* o = obs + (size_t)(t + 1) * 3;

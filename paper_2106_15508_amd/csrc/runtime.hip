@@ -14,6 +14,7 @@
 #include "abcsmc.h"
 #include "kernels.h"
 #include "ctx.h"
+#include "predict.h"
 
 using namespace abcsmc;
 using namespace abcsmc::rt;
@@ -564,6 +565,52 @@ int abcsmc_population(const abcsmc_ctx* cx, double* u, double* sigma, int64_t* p
     HIPCHK(x, hipStreamSynchronize(s));
     for (size_t k = 0; k < pi.size(); ++k) parent[k] = pi[k];
     for (size_t k = 0; k < ii.size(); ++k) index[k] = ii[k];
+    return ABCSMC_OK;
+}
+
+int abcsmc_predict(const abcsmc_ctx* cx, int32_t n_days, uint64_t seed, int32_t n_quant, const double* quant,
+                   double* bands)
+{
+    abcsmc_ctx* x = const_cast<abcsmc_ctx*>(cx);
+    if (!x) return fail(nullptr, ABCSMC_EINVAL, "ctx is NULL");
+    if (x->broken) return fail(&x->err, ABCSMC_ESTATE, "context unusable after a device error");
+    if (x->rounds == 0) return fail(&x->err, ABCSMC_ESTATE, "no completed stage");
+    if (n_days < 1 || n_days > 4096) return fail(&x->err, ABCSMC_EINVAL, "n_days must be in [1, 4096]");
+    if (n_quant < 1 || n_quant > 64 || !quant || !bands) return fail(&x->err, ABCSMC_EINVAL, "need 1..64 quantiles");
+    for (int k = 0; k < n_quant; ++k)
+        if (!(quant[k] >= 0.0 && quant[k] <= 1.0)) return fail(&x->err, ABCSMC_EINVAL, "quantiles must be in [0, 1]");
+    const size_t N = (size_t)x->N;
+    const size_t rows = (size_t)3 * (n_days + 1);
+    const size_t bytes = rows * N * 8 + 64 * 8 + rows * 64 * 8;
+    char* mem = nullptr;
+    if (hipMalloc((void**)&mem, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(&x->err, ABCSMC_ENOMEM, "hipMalloc of the predictive series failed");
+    }
+    PredictArgs a{};
+    a.m = x->model;
+    a.m.T = n_days;
+    a.u = x->pop[x->cur].u;
+    a.n = (int64_t)N;
+    a.round = kPredictRound;
+    a.m.seed = seed;
+    a.series = (double*)mem;
+    a.quant = (const double*)(mem + rows * N * 8);
+    a.n_quant = n_quant;
+    a.bands = (double*)(mem + rows * N * 8 + 64 * 8);
+    hipStream_t s = x->stream;
+    hipError_t e = hipMemcpyAsync((void*)a.quant, quant, (size_t)n_quant * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        launch_predict(a, s);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(bands, a.bands, rows * (size_t)n_quant * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(mem);
+    if (e != hipSuccess) {
+        x->broken = true;
+        return fail(&x->err, ABCSMC_EDEVICE, std::string("predictive simulation: ") + hipGetErrorString(e));
+    }
     return ABCSMC_OK;
 }
 

@@ -194,3 +194,19 @@ def test_mcmc_variant_bitwise(oracle, wl):
         assert _bits([infos[i]["mcmc_s"]])[0] == _bits([ref.mcmc_s[i]])[0], i
         assert infos[i]["simulated"] == ref.simulated[i], i
         assert infos[i]["invalid"] == ref.invalid[i], i
+
+
+@pytest.mark.parametrize("wl,days", [(W.tiny(n_rounds=3), 45), (W.C1.with_(n_rounds=2), 80)])
+def test_predictive_bands_bitwise(oracle, wl, days):
+    """Posterior predictive bands (Fig. 7) past the fitted horizon: the
+    oracle's own run and predictive simulations against the GPU's."""
+    obs = oracle.observations(wl)
+    ref = oracle.run(wl, obs)
+    q = (0.005, 0.25, 0.5, 0.75, 0.995, 0.0, 1.0)
+    want = oracle.predict(wl, obs, ref.u[-1], days, seed=77, quantiles=q)
+    with A.Context(wl, obs) as ctx:
+        ctx.run(wl.n_rounds)
+        got = ctx.predict(days, seed=77, quantiles=q)
+    assert np.array_equal(_bits(got), _bits(want))
+    # day 0 is the observed initial state for every particle
+    assert np.all(got[0, :, :] == np.asarray(obs[0], dtype=np.float64)[:, None])

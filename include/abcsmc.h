@@ -54,12 +54,16 @@ enum {
 enum {
     ABCSMC_STEP_PAPER = 0, /* eq. 16: s ~ Beta(eps_i / eps_1, 2 i) in stage i >= 1 */
     ABCSMC_STEP_FIXED = 1, /* s ~ Beta(beta_a, beta_b) in every stage */
-    ABCSMC_STEP_MCMC = 2   /* the paper's baseline (§II-D, eqs. 12-15): one step size s for every
+    ABCSMC_STEP_MCMC = 2,  /* the paper's baseline (§II-D, eqs. 12-15): one step size s for every
                               proposal of a batch ("run"); after each of the first mcmc_tune batches
                               of stages >= 1, s <- s (1 + (A - 0.234) / (0.766 (n_acc + 1))) with A =
                               accepted / valid proposals of the batch and n_acc the acceptances of
                               all tuned batches so far; needs batch > 0 (whole batches are simulated,
                               so results depend on it); single-run contexts only */
+    ABCSMC_STEP_MEANVAR = 3,   /* alternative Beta parameterisation (§III-B), mean and variance from the
+                                  same two quantities as eq. 16: mean mu = (eps_i/eps_1)/3, variance
+                                  mu (1 - mu) / (3 i + 1); real shapes, gamma-ratio sampler */
+    ABCSMC_STEP_MODECONC = 4   /* mode-concentration: mode (eps_i/eps_1)/4, concentration 2 i + 2 */
 };
 
 /* Transition sampler of the simulator (§II-B). */
@@ -126,6 +130,7 @@ typedef struct {
     int64_t weight_terms;         /* terms actually evaluated (the rest lie outside every window and
                                      are exactly zero) */
     double mcmc_s;                /* STEP_MCMC: step size after this stage (0 otherwise) */
+    double beta_b_real;           /* Beta shape b as a real number (STEP_MEANVAR / STEP_MODECONC) */
 } abcsmc_round_info;
 
 typedef struct abcsmc_ctx abcsmc_ctx;
@@ -198,7 +203,9 @@ int abcsmc_simulate(const abcsmc_config* cfg, int64_t n, const double* theta, co
  *  fn 9: Box-Muller pair                                    (in: uint64[n]; out: double[2n])
  *  fn 10: binomial draw                                     (in: {int64 n, double p, uint64 w}[n] as 3 x 8 bytes; out: int64[n])
  *  fn 11: Beta(a, b) draw, a = param_a, b = param_b          (in: uint64[n*b]; out: double[n])
- *  fn 12: floor-normal draw                                 (in: {int64 n, double h, uint64 w}[n]; out: int64[n]) */
+ *  fn 12: floor-normal draw                                 (in: {int64 n, double h, uint64 w}[n]; out: int64[n])
+ *  fn 13: real-shape Beta draw (gamma ratio)                 (in: double[2] = {a, b}; out: double[n]; draw i
+ *         uses stream (seed = param_a, particle i, round = param_b, PERTURB, attempt 0)) */
 int abcsmc_debug_eval(int32_t fn, int64_t n, const void* in, void* out, double param_a, int32_t param_b);
 
 /* ---------------------------------------------------------------------------

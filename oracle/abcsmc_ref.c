@@ -299,6 +299,45 @@ double ref_beta_int(double a, int b, const uint64_t* words)
     return ref_exp(L);
 }
 
+/* Gamma(k) by Marsaglia & Tsang (ACM TOMS 2000): for k >= 1, d = k - 1/3,
+ * c = 1/sqrt(9 d); iteration m takes z from word w0 + 2m (first Box-Muller
+ * normal) and U from word w0 + 2m + 1; v = (1 + c z)^3; accept d v when
+ * v > 0 and log U < z^2/2 + d - d v + d log v.  After 32 rejections (chance
+ * below 1e-40) the value is d.  For k < 1: Gamma(k + 1) U^(1/k) with U from
+ * word w0 + 64.  Words are those of stream (seed, index, round, PERTURB,
+ * sub). */
+double ref_gamma_mt(double k, uint64_t seed, uint32_t index, uint32_t round, uint32_t sub, uint32_t w0)
+{
+    const double kk = k < 1.0 ? k + 1.0 : k;
+    const double d = kk - 1.0 / 3.0;
+    const double c = 1.0 / sqrt(9.0 * d);
+    double g = d;
+    for (uint32_t m = 0; m < 32; ++m) {
+        double z, z_unused;
+        ref_box_muller(ref_word(seed, index, round, REF_PERTURB, sub, w0 + 2 * m), &z, &z_unused);
+        const double t = 1.0 + c * z;
+        if (!(t > 0.0)) continue;
+        const double v = t * t * t;
+        const double U = ref_u01(ref_word(seed, index, round, REF_PERTURB, sub, w0 + 2 * m + 1));
+        if (ref_log(U) < 0.5 * (z * z) + d - d * v + d * ref_log(v)) {
+            g = d * v;
+            break;
+        }
+    }
+    if (k < 1.0) g = g * ref_exp(ref_log(ref_u01(ref_word(seed, index, round, REF_PERTURB, sub, w0 + 64))) / k);
+    return g;
+}
+
+/* Beta(a, b) for real shapes: X / (X + Y) with X ~ Gamma(a) from words 5..,
+ * Y ~ Gamma(b) from words 70.. of the attempt's stream; 0 if both vanish. */
+double ref_beta_general(double a, double b, uint64_t seed, uint32_t index, uint32_t round, uint32_t sub)
+{
+    const double X = ref_gamma_mt(a, seed, index, round, sub, 5);
+    const double Y = ref_gamma_mt(b, seed, index, round, sub, 70);
+    const double s = X + Y;
+    return s > 0.0 ? X / s : 0.0;
+}
+
 /* ------------------------------------------------------------------ */
 /* Stochastic epidemic model (§II-B, eqs. 1-5)                          */
 /* ------------------------------------------------------------------ */
@@ -319,6 +358,7 @@ typedef struct {
     int64_t batch;                     /* simulations per run (schedule 2: one s per batch) */
     double mcmc_s0;                    /* schedule 2: initial step size s */
     int32_t mcmc_tune;                 /* schedule 2: batches of stages >= 1 after which s is adapted */
+    double beta_b_real;                /* schedules 3, 4: the stage's real Beta shape b (set by ref_run) */
 } ref_config;
 
 enum { REF_S = 0, REF_I, REF_A, REF_R, REF_D, REF_RU };
@@ -501,6 +541,32 @@ int64_t ref_parent(const uint64_t* C, int64_t n, uint64_t R)
 
 /* eq. 16 step-size law for stage i >= 1: Beta(eps_i/eps_1, 2i); or a fixed
  * Beta(a, b). */
+/* Alternative parameterisations of the step-size Beta (§III-B, stated
+ * without formulas): the two tuned quantities of eq. 16 -- the tolerance
+ * ratio r = eps_i / eps_1 and the stage i -- set
+ *   schedule 3, mean-variance: mean mu = r / 3 (at least 1e-12), variance mu (1 - mu) / (3 i + 1)
+ *     -> a = mu k, b = (1 - mu) k with k = mu (1 - mu) / variance - 1 = 3 i
+ *   schedule 4, mode-concentration: mode w = r / 4, concentration k = 2 i + 2
+ *     -> a = w (k - 2) + 1, b = (1 - w) (k - 2) + 1
+ * (both give the stage-1 shape a mean near that of eq. 16's Beta(1, 2)). */
+void ref_beta_shape_real(const ref_config* cfg, int32_t round, double eps_i, double eps_1, double* a, double* b)
+{
+    const double r = eps_i / eps_1;
+    if (cfg->step_schedule == 3) {
+        double mu = r / 3.0;
+        if (mu < 1e-12) mu = 1e-12; /* a stage with eps_i = 0 */
+        const double var = mu * (1.0 - mu) / (3.0 * (double)round + 1.0);
+        const double k = mu * (1.0 - mu) / var - 1.0;
+        *a = mu * k;
+        *b = (1.0 - mu) * k;
+    } else {
+        const double w = r / 4.0;
+        const double k = 2.0 * (double)round + 2.0;
+        *a = w * (k - 2.0) + 1.0;
+        *b = (1.0 - w) * (k - 2.0) + 1.0;
+    }
+}
+
 void ref_beta_shape(const ref_config* cfg, int32_t round, double eps_i, double eps_1,
                     double* a, int32_t* b)
 {
@@ -528,12 +594,15 @@ int32_t ref_perturb(const ref_config* cfg, uint32_t round, uint32_t index, const
 {
     uint64_t words[5 + 128];
     const int fixed_s = cfg->step_schedule == 2; /* MCMC variant: s = beta_a, no Beta words */
+    const int general = cfg->step_schedule >= 3; /* real shapes: beta_a and beta_b_real */
     for (int32_t att = 0; att < cfg->max_attempts; ++att) {
-        int nw = 5 + (fixed_s ? 0 : beta_b);
+        int nw = 5 + ((fixed_s || general) ? 0 : beta_b);
         for (int k = 0; k < nw; ++k)
             words[k] = ref_word(cfg->seed, index, round, REF_PERTURB, (uint32_t)att, (uint32_t)k);
         int64_t parent = ref_parent(C, n_prev, words[0]);
-        double s = fixed_s ? beta_a : ref_beta_int(beta_a, beta_b, words + 5);
+        double s = fixed_s ? beta_a
+                 : general ? ref_beta_general(beta_a, cfg->beta_b_real, cfg->seed, index, round, (uint32_t)att)
+                           : ref_beta_int(beta_a, beta_b, words + 5);
         double sigma = cfg->step_is_variance ? sqrt(s) : s;
         if (sigma < 1e-8) sigma = 1e-8;
         double z[REF_NPAR];
@@ -661,6 +730,7 @@ typedef struct {
     int64_t* attempts_total;
     double* ess;
     double* mcmc_s;   /* schedule 2: step size after stage r (its starting value for stage 0) */
+    double* beta_b_real; /* Beta shape b of stage r as a real number (schedules 3, 4: not an integer) */
     int64_t* simulated; /* proposals simulated: whole batches for schedule 2, else = proposals */
 } ref_result;
 
@@ -676,6 +746,7 @@ int ref_run(const ref_config* cfg, const int64_t* obs, int32_t n_rounds, ref_res
     uint64_t* C = (uint64_t*)malloc((size_t)N * sizeof(uint64_t));
     int rc = 0;
     double eps1 = INFINITY;
+    ref_config stage_cfg = *cfg;   /* schedules 3, 4: carries the stage's real shape b */
     double s_mcmc = cfg->mcmc_s0;  /* schedule 2 state, carried across stages */
     int32_t tunes = 0;
     int64_t n_acc = 0;
@@ -711,14 +782,19 @@ int ref_run(const ref_config* cfg, const int64_t* obs, int32_t n_rounds, ref_res
             if (r == 1) eps1 = eps;
             double ba; int32_t bb;
             ref_beta_shape(cfg, r, eps, eps1, &ba, &bb);
+            if (cfg->step_schedule >= 3) {
+                ref_beta_shape_real(cfg, r, eps, eps1, &ba, &stage_cfg.beta_b_real);
+                bb = 0;
+            }
             out->beta_a[r] = ba;
             out->beta_b[r] = bb;
+            out->beta_b_real[r] = cfg->step_schedule >= 3 ? stage_cfg.beta_b_real : (double)bb;
             ref_resample_weights(d_prev, N, eps, q, C);
             if (cfg->step_schedule != 2) {
                 while (accepted < N) {
                     if (j >= cfg->max_proposals) { rc = -4; break; }
                     double uj[REF_NPAR], s; int64_t parent;
-                    int32_t a = ref_perturb(cfg, (uint32_t)r, (uint32_t)j, u_prev, C, N, ba, bb, uj, &s, &parent);
+                    int32_t a = ref_perturb(&stage_cfg, (uint32_t)r, (uint32_t)j, u_prev, C, N, ba, bb, uj, &s, &parent);
                     att_total += a > 0 ? a : -a;
                     if (a < 0) { ++invalid; ++j; continue; }
                     double d = ref_sim_distance(cfg, obs, uj, (uint32_t)r, (uint32_t)j, traj);
@@ -778,7 +854,7 @@ int ref_run(const ref_config* cfg, const int64_t* obs, int32_t n_rounds, ref_res
                 lw[k] = ref_log_weight(u + (size_t)k * REF_NPAR, sig[k], u_prev, q, N);
             out->ess[r] = ref_normalise(lw, N, W);
         }
-        if (r == 0) { out->ess[0] = (double)N; out->simulated[0] = N; }
+        if (r == 0) { out->ess[0] = (double)N; out->simulated[0] = N; out->beta_b_real[0] = 0.0; }
         out->mcmc_s[r] = s_mcmc;
         out->proposals[r] = j;
         out->invalid[r] = invalid;
@@ -827,3 +903,16 @@ void ref_beta_many(double a, int32_t b, const uint64_t* words, double* out, int6
 {
     for (int64_t i = 0; i < cnt; ++i) out[i] = ref_beta_int(a, b, words + (size_t)i * b);
 }
+
+/* n general Beta(a, b) draws: draw i uses stream (seed, index0 + i, round, PERTURB, sub) */
+void ref_beta_general_many(double a, double b, uint64_t seed, uint32_t index0, uint32_t round, uint32_t sub,
+                           double* out, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = ref_beta_general(a, b, seed, index0 + (uint32_t)i, round, sub);
+}
+
+void ref_gamma_many(double k, uint64_t seed, uint32_t index0, uint32_t round, uint32_t sub, double* out, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = ref_gamma_mt(k, seed, index0 + (uint32_t)i, round, sub, 5);
+}
+

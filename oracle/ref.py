@@ -40,6 +40,7 @@ class Config(C.Structure):
         ("beta_b", C.c_int32), ("step_is_variance", C.c_int32), ("sampler", C.c_int32),
         ("max_attempts", C.c_int32), ("seed", C.c_uint64), ("max_proposals", C.c_int64),
         ("batch", C.c_int64), ("mcmc_s0", C.c_double), ("mcmc_tune", C.c_int32),
+        ("beta_b_real", C.c_double),
     ]
 
 
@@ -49,7 +50,7 @@ class Result(C.Structure):
         ("index", C.c_void_p), ("attempts", C.c_void_p), ("logw", C.c_void_p), ("W", C.c_void_p),
         ("eps", C.c_void_p), ("eps_next", C.c_void_p), ("beta_a", C.c_void_p), ("beta_b", C.c_void_p),
         ("proposals", C.c_void_p), ("invalid", C.c_void_p), ("attempts_total", C.c_void_p),
-        ("ess", C.c_void_p), ("mcmc_s", C.c_void_p), ("simulated", C.c_void_p),
+        ("ess", C.c_void_p), ("mcmc_s", C.c_void_p), ("beta_b_real", C.c_void_p), ("simulated", C.c_void_p),
     ]
 
 
@@ -87,6 +88,9 @@ def lib():
             "ref_normalise": (d, [vp, i64, vp]),
             "ref_run": (i32, [vp, vp, i32, vp]),
             "ref_mcmc_update": (d, [d, i64, i64, i64]),
+            "ref_beta_general_many": (None, [d, d, u64, u32, u32, u32, vp, i64]),
+            "ref_gamma_many": (None, [d, u64, u32, u32, u32, vp, i64]),
+            "ref_beta_shape_real": (None, [vp, i32, d, d, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -242,6 +246,28 @@ def sim_distance(w, obs, u, rnd: int, index: int, **over) -> float:
     return lib().ref_sim_distance(C.byref(cfg), _p(obs), _p(u), rnd, index, _p(traj))
 
 
+def beta_general(a: float, b: float, seed: int, index0: int, rnd: int, sub: int, n: int) -> np.ndarray:
+    """n real-shape Beta(a, b) draws (gamma ratio, Marsaglia-Tsang), draw i on
+    stream (seed, index0 + i, rnd, PERTURB, sub)."""
+    out = np.zeros(n)
+    lib().ref_beta_general_many(a, b, seed, index0, rnd, sub, _p(out), n)
+    return out
+
+
+def gamma_mt(k: float, seed: int, index0: int, rnd: int, sub: int, n: int) -> np.ndarray:
+    out = np.zeros(n)
+    lib().ref_gamma_many(k, seed, index0, rnd, sub, _p(out), n)
+    return out
+
+
+def beta_shape_real(w, rnd: int, eps_i: float, eps_1: float):
+    """(a, b) of the alternative parameterisations (schedules 3, 4)."""
+    cfg = make_config(w)
+    a, b = C.c_double(), C.c_double()
+    lib().ref_beta_shape_real(C.byref(cfg), rnd, eps_i, eps_1, C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
 PREDICT_ROUND = 0xFFFE
 
 
@@ -302,6 +328,7 @@ class RunResult:
     attempts_total: np.ndarray
     ess: np.ndarray
     mcmc_s: np.ndarray
+    beta_b_real: np.ndarray
     simulated: np.ndarray
 
     def theta(self, w) -> np.ndarray:
@@ -322,7 +349,7 @@ def run(w, obs, n_rounds: Optional[int] = None, **over) -> RunResult:
         eps=np.zeros(R), eps_next=np.zeros(R), beta_a=np.zeros(R), beta_b=np.zeros(R, np.int32),
         proposals=np.zeros(R, np.int64), invalid=np.zeros(R, np.int64),
         attempts_total=np.zeros(R, np.int64), ess=np.zeros(R), mcmc_s=np.zeros(R),
-        simulated=np.zeros(R, np.int64),
+        beta_b_real=np.zeros(R), simulated=np.zeros(R, np.int64),
     )
     res = Result(**{k: v.ctypes.data for k, v in arrs.items()})
     obs = np.ascontiguousarray(obs, dtype=np.int64)

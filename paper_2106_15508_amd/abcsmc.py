@@ -76,7 +76,7 @@ class RoundInfo(C.Structure):
         ("ms_simulate", C.c_double), ("ms_weights", C.c_double), ("ms_select", C.c_double),
         ("ms_total", C.c_double), ("ms_k_propose", C.c_double), ("ms_k_weights", C.c_double),
         ("n_k_propose", C.c_int64), ("sim_days", C.c_int64), ("weight_pairs", C.c_int64),
-        ("weight_terms", C.c_int64), ("mcmc_s", C.c_double),
+        ("weight_terms", C.c_int64), ("mcmc_s", C.c_double), ("beta_b_real", C.c_double),
     ]
 
     def as_dict(self):

@@ -328,7 +328,8 @@ __global__ __launch_bounds__(kBlock) void propose_persistent_kernel(BatchArgs a)
                                   S.beta_a,
                                   S.beta_b,
                                   R.step_is_variance,
-                                  -1.0};
+                                  -1.0,
+                                  0.0};
         lane::ProposalOut o;
         if (R.m.sampler == 0) lane::propose_one<kRound0, 0>(R.m, in, p, o);
         else lane::propose_one<kRound0, 1>(R.m, in, p, o);

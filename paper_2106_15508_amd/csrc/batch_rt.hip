@@ -121,8 +121,8 @@ WinLayout win_layout(size_t o, size_t n_total, size_t n_fin)
 int bvalidate(const abcsmc_config& c, const int64_t* obs, std::string* e)
 {
     size_t dummy;
-    if (c.step_schedule == ABCSMC_STEP_MCMC)
-        return bfail(e, ABCSMC_EINVAL, "batched runs: the MCMC step schedule runs in single-run contexts only");
+    if (c.step_schedule != ABCSMC_STEP_PAPER && c.step_schedule != ABCSMC_STEP_FIXED)
+        return bfail(e, ABCSMC_EINVAL, "batched runs: eq. 16 or fixed Beta step schedules only");
     abcsmc_config cc = c;
     cc.batch = 0;
     const int rc = abcsmc_workspace_size(&cc, &dummy);

@@ -284,6 +284,52 @@ __device__ __forceinline__ double normal_one(uint64_t w)
 
 // ---------------------------------------------------------------- samplers
 
+// Word w of stream (index, round, purpose, sub): half w % 2 of block w / 2.
+__device__ __forceinline__ uint64_t word_at(uint64_t seed, uint32_t index, uint32_t round, uint32_t purpose,
+                                            uint32_t sub, uint32_t w)
+{
+    const w2 b = block_words(seed, index, round, purpose, sub, w >> 1);
+    return (w & 1u) ? b.b : b.a;
+}
+
+// Gamma(k) by Marsaglia & Tsang (ACM TOMS 2000): k' = k (k + 1 if k < 1),
+// d = k' - 1/3, c = 1/sqrt(9 d); iteration m: z = first Box-Muller normal of
+// word w0 + 2m, U from word w0 + 2m + 1, v = (1 + c z)^3, accept d v when
+// v > 0 and log U < z^2/2 + d - d v + d log v; d after 32 rejections.  For
+// k < 1 the result is scaled by U^(1/k), U from word w0 + 64.
+__device__ __forceinline__ double gamma_mt(double k, uint64_t seed, uint32_t index, uint32_t round, uint32_t sub,
+                                           uint32_t w0)
+{
+    const double kk = k < 1.0 ? k + 1.0 : k;
+    const double d = kk - 1.0 / 3.0;
+    const double c = 1.0 / __builtin_sqrt(9.0 * d);
+    double g = d;
+    for (uint32_t m = 0; m < 32; ++m) {
+        const double z = normal_one(word_at(seed, index, round, kPerturb, sub, w0 + 2 * m));
+        const double t = 1.0 + c * z;
+        if (!(t > 0.0)) continue;
+        const double v = t * t * t;
+        const double U = u01(word_at(seed, index, round, kPerturb, sub, w0 + 2 * m + 1));
+        if (log(U) < 0.5 * (z * z) + d - d * v + d * log(v)) {
+            g = d * v;
+            break;
+        }
+    }
+    if (k < 1.0) g = g * exp(log(u01(word_at(seed, index, round, kPerturb, sub, w0 + 64))) / k);
+    return g;
+}
+
+// Beta(a, b), real shapes: X / (X + Y), X ~ Gamma(a) from words 5.., Y ~
+// Gamma(b) from words 70.. of the attempt's PERTURB stream; 0 if both vanish.
+__device__ __forceinline__ double beta_general(double a, double b, uint64_t seed, uint32_t index, uint32_t round,
+                                               uint32_t sub)
+{
+    const double X = gamma_mt(a, seed, index, round, sub, 5);
+    const double Y = gamma_mt(b, seed, index, round, sub, 70);
+    const double s = X + Y;
+    return s > 0.0 ? X / s : 0.0;
+}
+
 constexpr double kTSwitch = 10.0;
 constexpr int kBinvCap = 128;
 

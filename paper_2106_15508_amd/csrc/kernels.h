@@ -64,6 +64,7 @@ struct ProposeArgs {
     int32_t beta_b;
     int32_t step_is_variance;
     double s_fixed;          // >= 0: every proposal uses step size s_fixed (MCMC variant), no Beta draw
+    double beta_b_real;      // > 0: real Beta shape b, general sampler (alternative parameterisations)
     // staging, indexed by p = j - base
     double* st_u;            // count x 8
     double* st_d;

@@ -74,6 +74,7 @@ struct PerturbArgs {
     double beta_a;
     int32_t beta_b;
     int32_t step_is_variance;
+    double beta_b_real;       // > 0: real Beta shape b
     double* pu;               // count x 8 proposals
     double* psigma;
     int32_t* pparent;

@@ -166,6 +166,7 @@ struct ProposalIn {
     int32_t beta_b;
     int32_t step_is_variance;
     double s_fixed;          // >= 0: step size of every proposal (MCMC variant); < 0: Beta draw
+    double beta_b_real;      // > 0: real Beta shape b (general sampler; beta_b unused)
 };
 
 struct ProposalOut {
@@ -217,7 +218,7 @@ __device__ __forceinline__ void perturb_one(const Model& m, const ProposalIn& a,
                 // Beta(a, b), b integer: exp( sum_m log U_m / (a + m) )
                 double L = 0.0;
                 uint64_t hold = 0;
-                const int32_t nb = a.s_fixed >= 0.0 ? 0 : a.beta_b;
+                const int32_t nb = (a.s_fixed >= 0.0 || a.beta_b_real > 0.0) ? 0 : a.beta_b;
                 for (int32_t mm = 0; mm < nb; ++mm) {
                     uint64_t w;
                     if (mm == 0) {
@@ -232,7 +233,10 @@ __device__ __forceinline__ void perturb_one(const Model& m, const ProposalIn& a,
                     }
                     L = L + dm::log(dm::u01(w)) / (a.beta_a + (double)mm);
                 }
-                const double s = a.s_fixed >= 0.0 ? a.s_fixed : dm::exp(L);
+                const double s = a.s_fixed >= 0.0       ? a.s_fixed
+                                 : a.beta_b_real > 0.0 ? dm::beta_general(a.beta_a, a.beta_b_real, m.seed, j,
+                                                                          a.round, sub)
+                                                       : dm::exp(L);
                 double sg = a.step_is_variance ? __builtin_sqrt(s) : s;
                 if (sg < 1e-8) sg = 1e-8;
                 double z[kNP];

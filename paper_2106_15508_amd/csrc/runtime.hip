@@ -102,8 +102,7 @@ int validate(const abcsmc_config* c, const int64_t* obs, std::string* err)
     if (c->n_particles < 2 || c->n_particles > ((int64_t)1 << 22)) return fail(err, ABCSMC_EINVAL, "n_particles must be in [2, 2^22]");
     if (c->batch < 0 || c->batch > ((int64_t)1 << 24)) return fail(err, ABCSMC_EINVAL, "batch must be in [0, 2^24]");
     if (!(c->surv_ratio > 0.0 && c->surv_ratio < 1.0)) return fail(err, ABCSMC_EINVAL, "surv_ratio must be in (0,1)");
-    if (c->step_schedule != ABCSMC_STEP_PAPER && c->step_schedule != ABCSMC_STEP_FIXED &&
-        c->step_schedule != ABCSMC_STEP_MCMC)
+    if (c->step_schedule < ABCSMC_STEP_PAPER || c->step_schedule > ABCSMC_STEP_MODECONC)
         return fail(err, ABCSMC_EINVAL, "unknown step_schedule");
     if (c->step_schedule == ABCSMC_STEP_MCMC &&
         (c->batch <= 0 || !(c->mcmc_s0 > 0.0) || !std::isfinite(c->mcmc_s0) || c->mcmc_tune < 0))
@@ -311,9 +310,28 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
     hipStream_t s = x->stream;
 
     const double eps = r == 0 ? INFINITY : x->eps_next;
-    double ba = 0.0;
+    double ba = 0.0, bb_real = 0.0;
     int32_t bb = 0;
-    if (r > 0 && c.step_schedule != ABCSMC_STEP_MCMC) {
+    const bool general = c.step_schedule == ABCSMC_STEP_MEANVAR || c.step_schedule == ABCSMC_STEP_MODECONC;
+    if (r > 0 && general) {
+        // alternative parameterisations of the step-size Beta from the two
+        // quantities eq. 16 tunes: the tolerance ratio and the stage index
+        const double e1 = r == 1 ? eps : x->eps1;
+        const double ratio = eps / e1;
+        if (c.step_schedule == ABCSMC_STEP_MEANVAR) {
+            double mu = ratio / 3.0;                                           // mean
+            if (mu < 1e-12) mu = 1e-12;                                        // eps_i = 0
+            const double var = mu * (1.0 - mu) / (3.0 * (double)r + 1.0);       // variance
+            const double k = mu * (1.0 - mu) / var - 1.0;
+            ba = mu * k;
+            bb_real = (1.0 - mu) * k;
+        } else {
+            const double w = ratio / 4.0;                                       // mode
+            const double k = 2.0 * (double)r + 2.0;                             // concentration
+            ba = w * (k - 2.0) + 1.0;
+            bb_real = (1.0 - w) * (k - 2.0) + 1.0;
+        }
+    } else if (r > 0 && c.step_schedule != ABCSMC_STEP_MCMC) {
         if (c.step_schedule == ABCSMC_STEP_FIXED) {
             ba = c.beta_a;
             bb = c.beta_b;
@@ -358,6 +376,7 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
     pa.step_is_variance = (c.flags & ABCSMC_F_STEP_IS_VARIANCE) ? 1 : 0;
     const bool mcmc = c.step_schedule == ABCSMC_STEP_MCMC;
     pa.s_fixed = (mcmc && r > 0) ? x->mcmc_s : -1.0;
+    pa.beta_b_real = (general && r > 0) ? bb_real : 0.0;
     pa.st_u = x->at<double>(x->L.st_u);
     pa.st_d = x->at<double>(x->L.st_d);
     pa.st_sigma = x->at<double>(x->L.st_sigma);
@@ -515,6 +534,7 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
         I.weight_pairs = r == 0 ? 0 : (int64_t)N * (int64_t)hc.survivors;
         I.weight_terms = (int64_t)hterms;
         I.mcmc_s = mcmc ? x->mcmc_s : 0.0;
+        I.beta_b_real = general ? bb_real : (double)bb;
     }
     return ABCSMC_OK;
 }
@@ -688,7 +708,9 @@ int abcsmc_simulate(const abcsmc_config* cfg, int64_t n, const double* theta, co
 
 int abcsmc_debug_eval(int32_t fn, int64_t n, const void* in, void* out, double param_a, int32_t param_b)
 {
-    if (n < 1 || !in || !out || fn < 0 || fn > 12) return fail(nullptr, ABCSMC_EINVAL, "bad debug_eval arguments");
+    if (n < 1 || !in || !out || fn < 0 || fn > 13) return fail(nullptr, ABCSMC_EINVAL, "bad debug_eval arguments");
+    if (fn == 13 && (!(param_a >= 0.0) || param_a > 9007199254740992.0))
+        return fail(nullptr, ABCSMC_EINVAL, "seed must be an integer-valued double in [0, 2^53]");
     if (fn == 11 && (param_b < 1 || param_b > 128)) return fail(nullptr, ABCSMC_EINVAL, "beta b out of range");
     size_t in_b = 0, out_b = 0;
     switch (fn) {
@@ -697,6 +719,7 @@ int abcsmc_debug_eval(int32_t fn, int64_t n, const void* in, void* out, double p
     case 9: in_b = 8 * n; out_b = 16 * n; break;
     case 10: case 12: in_b = 24 * n; out_b = 8 * n; break;
     case 11: in_b = 8 * (size_t)n * param_b; out_b = 8 * n; break;
+    case 13: in_b = 16; out_b = 8 * n; break;
     default: in_b = 8 * n; out_b = 8 * n; break;
     }
     void *din = nullptr, *dout = nullptr;

@@ -30,7 +30,7 @@ __global__ __launch_bounds__(kBlock) void perturb_only_kernel(PerturbArgs a)
     bool valid = false;
     if (active) {
         const lane::ProposalIn in{nullptr, a.round, a.max_attempts, 0.0, 0.0, a.u_prev, a.cdf, a.n_prev,
-                                  a.beta_a, a.beta_b, a.step_is_variance, -1.0};
+                                  a.beta_a, a.beta_b, a.step_is_variance, -1.0, a.beta_b_real};
         lane::ProposalOut o;
         lane::perturb_one<false>(a.m, in, a.base + p, o);
         double* u = a.pu + (size_t)p * kNP;

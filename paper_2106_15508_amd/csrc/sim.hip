@@ -28,7 +28,7 @@ void propose_kernel(ProposeArgs a)
     const bool active = p < a.count;
     const uint32_t j = a.base + p;
     const lane::ProposalIn in{a.obs,    a.round,  a.max_attempts, a.eps,   a.exit_thr,          a.u_prev,
-                              a.cdf,    a.n_prev, a.beta_a,       a.beta_b, a.step_is_variance, a.s_fixed};
+                              a.cdf,    a.n_prev, a.beta_a,       a.beta_b, a.step_is_variance, a.s_fixed, a.beta_b_real};
     lane::ProposalOut o;
     o.valid = false;
     o.acc = false;
@@ -162,6 +162,10 @@ __global__ __launch_bounds__(kBlock) void debug_eval_kernel(int32_t fn, int64_t 
         const uint64_t w = ((const uint64_t*)in)[3 * i + 2];
         const double r = fn == 10 ? dm::binomial((double)nn, pp, w) : dm::normal_floor((double)nn, pp, w);
         ((int64_t*)out)[i] = (int64_t)r;
+    } break;
+    case 13: {
+        const double* ab = (const double*)in;
+        y[i] = dm::beta_general(ab[0], ab[1], (uint64_t)pa, (uint32_t)i, (uint32_t)pb, 0);
     } break;
     case 11: {
         const uint64_t* w = (const uint64_t*)in + (size_t)i * pb;

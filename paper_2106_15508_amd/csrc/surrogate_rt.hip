@@ -234,6 +234,7 @@ int surrogate_batches(abcsmc_ctx* x, const ProposeArgs& pa, const DevPop& dst, i
     qa.beta_a = pa.beta_a;
     qa.beta_b = pa.beta_b;
     qa.step_is_variance = pa.step_is_variance;
+    qa.beta_b_real = pa.beta_b_real;
     qa.pu = S.pu;
     qa.psigma = S.psigma;
     qa.pparent = S.pparent;

@@ -76,8 +76,8 @@ __device__ __forceinline__ void fill_table(double* T)
 
 // Sum over the sorted columns [k0, k1) for this lane's row, in 256-column
 // tiles; a tile that no row of the wave can reach (sort coordinate outside
-// [wlo, whi]) is skipped.  Two interleaved partial sums, the next pair of
-// columns loaded before the current pair is used.
+// [wlo, whi]) is skipped.  Two interleaved partial sums (even and odd
+// columns), four columns' scalar loads issued together per step.
 __device__ __forceinline__ double row_sum(const double* uj, double cj, const_col_ptr cols, const_col_ptr skey,
                                           int k0, int k1, double wlo, double whi, const double* T,
                                           const double* ex, unsigned long long lanes,
@@ -89,21 +89,19 @@ __device__ __forceinline__ double row_sum(const double* uj, double cj, const_col
         if (skey[c0 + n - 1] < wlo || skey[c0] > whi) continue;
         evaluated += lanes * (unsigned long long)n;
         double p0 = 0.0, p1 = 0.0;
-        Col ca = load_col(cols, __builtin_amdgcn_readfirstlane(c0));
-        Col cb = load_col(cols, __builtin_amdgcn_readfirstlane(c0 + (n > 1 ? 1 : 0)));
         int cc = 0;
-        for (; cc + 1 < n; cc += 2) {
-            const int kn = __builtin_amdgcn_readfirstlane(c0 + (cc + 3 < n ? cc + 2 : cc));
-            const Col na = load_col(cols, kn);
-            const Col nb = load_col(cols, kn + (cc + 3 < n ? 1 : 0));
-            p0 += term_c(uj, cj, ca, T, ex);
-            p1 += term_c(uj, cj, cb, T, ex);
-            ca = na;
-            cb = nb;
+        for (; cc + 3 < n; cc += 4) {
+            const int k = __builtin_amdgcn_readfirstlane(c0 + cc);
+            const Col a0 = load_col(cols, k), a1 = load_col(cols, k + 1), a2 = load_col(cols, k + 2), a3 = load_col(cols, k + 3);
+            p0 += term_c(uj, cj, a0, T, ex);
+            p1 += term_c(uj, cj, a1, T, ex);
+            p0 += term_c(uj, cj, a2, T, ex);
+            p1 += term_c(uj, cj, a3, T, ex);
         }
-        if (cc < n) {
-            ca = load_col(cols, __builtin_amdgcn_readfirstlane(c0 + cc));
-            p0 += term_c(uj, cj, ca, T, ex);
+        for (; cc < n; cc += 2) {
+            const int k = __builtin_amdgcn_readfirstlane(c0 + cc);
+            p0 += term_c(uj, cj, load_col(cols, k), T, ex);
+            if (cc + 1 < n) p1 += term_c(uj, cj, load_col(cols, k + 1), T, ex);
         }
         total += p0 + p1;
     }

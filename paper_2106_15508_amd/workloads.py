@@ -42,6 +42,8 @@ OBS_ROUND = 0xFFFF
 STEP_PAPER = 0   # eq. (16): Beta(eps_i / eps_1, 2 i)
 STEP_FIXED = 1   # Beta(beta_a, beta_b) in every round
 STEP_MCMC = 2    # one MCMC-tuned step size s per batch (eqs. 12-15); batch > 0
+STEP_MEANVAR = 3   # Beta by mean (eps_i/eps_1)/3 and variance mu(1-mu)/(3i+1)
+STEP_MODECONC = 4  # Beta by mode (eps_i/eps_1)/4 and concentration 2i+2
 SAMPLER_BINOMIAL = 0
 SAMPLER_NORMAL_FLOOR = 1
 

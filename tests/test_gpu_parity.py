@@ -210,3 +210,20 @@ def test_predictive_bands_bitwise(oracle, wl, days):
     assert np.array_equal(_bits(got), _bits(want))
     # day 0 is the observed initial state for every particle
     assert np.all(got[0, :, :] == np.asarray(obs[0], dtype=np.float64)[:, None])
+
+
+@pytest.mark.parametrize("wl", [
+    W.tiny(step_schedule=W.STEP_MEANVAR),
+    W.tiny(step_schedule=W.STEP_MODECONC, seed=12),
+    W.C1.with_(step_schedule=W.STEP_MEANVAR, n_rounds=5),
+])
+def test_alternative_beta_parameterisations_bitwise(oracle, wl):
+    """Mean-variance and mode-concentration step-size Betas (real shapes,
+    gamma-ratio sampler): runs match the oracle bit for bit."""
+    obs = oracle.observations(wl)
+    ref = oracle.run(wl, obs)
+    assert ref.rc == 0
+    infos, pops = _gpu_run(wl, obs, wl.n_rounds)
+    _compare_run(oracle, wl, ref, infos, pops, wl.n_rounds)
+    for i in range(1, wl.n_rounds):
+        assert _bits([infos[i]["beta_b_real"]])[0] == _bits([ref.beta_b_real[i]])[0], i

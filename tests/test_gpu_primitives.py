@@ -118,3 +118,13 @@ def test_beta_bitwise(oracle, a, b):
     w = np.random.default_rng(int(a * 1000) + b).integers(0, 2**64, (cnt, b), dtype=np.uint64)
     got = _ev(11, w, cnt, np.float64, cnt, a, b)
     assert _same(got, oracle.beta_int(a, b, w))
+
+
+@pytest.mark.parametrize("a,b,seed,rnd", [(0.3, 2.7, 7, 3), (1.5, 2.5, 11, 1), (0.05, 14.9, 5, 9),
+                                           (2.2, 0.6, 1, 2), (7.0, 31.5, 3, 4)])
+def test_general_beta_bitwise(oracle, a, b, seed, rnd):
+    n = 5000
+    got = np.zeros(n)
+    A.debug_eval(13, np.array([a, b]), n, got, float(seed), rnd)
+    want = oracle.beta_general(a, b, seed, 0, rnd, 0, n)
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))

@@ -139,3 +139,30 @@ def test_beta_b1_is_power_of_uniform(oracle):
     for a in (0.3, 1.0, 2.5):
         s = oracle.beta_int(a, 1, w.reshape(-1, 1))
         np.testing.assert_allclose(s, u ** (1.0 / a), rtol=1e-14)
+
+
+# ---------------------------------------------------------------- real-shape Beta (alternative parameterisations)
+
+@pytest.mark.parametrize("a,b", [(0.3, 2.7), (1.5, 2.5), (0.05, 14.9), (2.2, 0.6), (7.0, 31.5)])
+def test_general_beta_matches_scipy(oracle, a, b):
+    x = oracle.beta_general(a, b, seed=7, index0=0, rnd=3, sub=0, n=20000)
+    assert np.all((x >= 0) & (x <= 1))
+    assert stats.kstest(x, "beta", args=(a, b)).pvalue > 1e-3
+
+
+@pytest.mark.parametrize("k", [0.4, 1.0, 3.7, 25.0])
+def test_gamma_marsaglia_tsang_matches_scipy(oracle, k):
+    g = oracle.gamma_mt(k, seed=9, index0=0, rnd=1, sub=0, n=20000)
+    assert stats.kstest(g, "gamma", args=(k,)).pvalue > 1e-3
+
+
+@pytest.mark.parametrize("stage,ratio", [(1, 1.0), (2, 0.43), (5, 0.05), (9, 0.002)])
+def test_alternative_parameterisations_closed_forms(oracle, stage, ratio):
+    from paper_2106_15508_amd import workloads as W
+    a, b = oracle.beta_shape_real(W.tiny(step_schedule=W.STEP_MEANVAR), stage, ratio, 1.0)
+    mu = ratio / 3
+    assert stats.beta(a, b).mean() == pytest.approx(mu, rel=1e-12)
+    assert stats.beta(a, b).var() == pytest.approx(mu * (1 - mu) / (3 * stage + 1), rel=1e-12)
+    a, b = oracle.beta_shape_real(W.tiny(step_schedule=W.STEP_MODECONC), stage, ratio, 1.0)
+    assert (a - 1) / (a + b - 2) == pytest.approx(ratio / 4, rel=1e-12)
+    assert a + b == pytest.approx(2 * stage + 2, rel=1e-12)

@@ -629,9 +629,10 @@ inline unsigned blocks_of(int64_t n, int per) { return (unsigned)((n + per - 1) 
 
 void weight_exp_constants(double ex[7])
 {
-    ex[0] = 0.6931471805599453 / 1024.0;  // ln2 / 1024 (exact scaling of the double ln 2)
-    ex[1] = 1.0 / 2.0;
-    ex[2] = 1.0 / 6.0;
+    const double L = 0.6931471805599453 / 1024.0;  // ln2 / 1024 (exact scaling of the double ln 2)
+    ex[0] = L;
+    ex[1] = (L * L) / 2.0;
+    ex[2] = (L * L * L) / 6.0;
     ex[3] = 1477.3197218702985;           // 1024 / ln 2
     ex[4] = ex[5] = ex[6] = 0.0;
 }

@@ -18,7 +18,8 @@ constexpr int kTile = 256;  // columns per skip-test tile
 //   t = D c_j with c_j = -1024 / (2 sigma_j^2 ln 2)  (the exponent in units
 //   of ln2/1024), k = rint(t), r = (t - k) ln2/1024, |r| <= 3.4e-4,
 //   exp = 2^(k >> 10) 2^((k & 1023)/1024) (1 + r + r^2/2 + r^3/6)
-// (truncation r^4/24 < 6e-16 relative).  There is no cut-off: a term with
+// (truncation r^4/24 < 6e-16 relative); the weight q_k enters by one fma
+// into the running sum.  There is no cut-off: a term with
 // exponent below -708 comes out as 0 or a subnormal-size value, which cannot
 // change a row sum (every row holds its own parent's term, >= e^-185) -- the
 // sums are those of the exact-zero convention.  For t below -2^31 the integer
@@ -43,8 +44,11 @@ __device__ __forceinline__ Col load_col(const_col_ptr cols, int k)
     return c;
 }
 
-// ex[0] = ln2/1024, ex[1] = 1/2, ex[2] = 1/6 (kernel arguments: SGPRs)
-__device__ __forceinline__ double term_c(const double* uj, double cj, const Col& c, const double* T, const double* ex)
+// exp of the term (without q): with f = t - k in [-1/2, 1/2] and L = ln2/1024,
+// e^(f L) = 1 + f (L + f (L^2/2 + f L^3/6)); ex[0..2] = L, L^2/2, L^3/6
+// (kernel arguments: SGPRs).
+__device__ __forceinline__ double term_exp(const double* uj, double cj, const Col& c, const double* T,
+                                           const double* ex)
 {
     double D = 0.0;
 #pragma unroll
@@ -54,12 +58,12 @@ __device__ __forceinline__ double term_c(const double* uj, double cj, const Col&
     }
     const double t = D * cj;
     const double kk = __builtin_rint(t);
-    const double r = (t - kk) * ex[0];
+    const double f = t - kk;
     const int ik = (int)kk;
-    double p = __builtin_fma(r, ex[2], ex[1]);
-    p = __builtin_fma(p, r, 1.0);
-    p = __builtin_fma(p, r, 1.0);
-    return c.q * __builtin_ldexp(T[ik & (kTab - 1)] * p, ik >> kTabBits);
+    double p = __builtin_fma(f, ex[2], ex[1]);
+    p = __builtin_fma(p, f, ex[0]);
+    p = __builtin_fma(p, f, 1.0);
+    return __builtin_ldexp(T[ik & (kTab - 1)] * p, ik >> kTabBits);
 }
 
 // Per-lane scale c_j of the row's exponent (ex[3] = 1024 / ln 2).
@@ -93,15 +97,19 @@ __device__ __forceinline__ double row_sum(const double* uj, double cj, const_col
         for (; cc + 3 < n; cc += 4) {
             const int k = __builtin_amdgcn_readfirstlane(c0 + cc);
             const Col a0 = load_col(cols, k), a1 = load_col(cols, k + 1), a2 = load_col(cols, k + 2), a3 = load_col(cols, k + 3);
-            p0 += term_c(uj, cj, a0, T, ex);
-            p1 += term_c(uj, cj, a1, T, ex);
-            p0 += term_c(uj, cj, a2, T, ex);
-            p1 += term_c(uj, cj, a3, T, ex);
+            p0 = __builtin_fma(a0.q, term_exp(uj, cj, a0, T, ex), p0);
+            p1 = __builtin_fma(a1.q, term_exp(uj, cj, a1, T, ex), p1);
+            p0 = __builtin_fma(a2.q, term_exp(uj, cj, a2, T, ex), p0);
+            p1 = __builtin_fma(a3.q, term_exp(uj, cj, a3, T, ex), p1);
         }
         for (; cc < n; cc += 2) {
             const int k = __builtin_amdgcn_readfirstlane(c0 + cc);
-            p0 += term_c(uj, cj, load_col(cols, k), T, ex);
-            if (cc + 1 < n) p1 += term_c(uj, cj, load_col(cols, k + 1), T, ex);
+            const Col a0 = load_col(cols, k);
+            p0 = __builtin_fma(a0.q, term_exp(uj, cj, a0, T, ex), p0);
+            if (cc + 1 < n) {
+                const Col a1 = load_col(cols, k + 1);
+                p1 = __builtin_fma(a1.q, term_exp(uj, cj, a1, T, ex), p1);
+            }
         }
         total += p0 + p1;
     }

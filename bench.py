@@ -46,10 +46,12 @@ FLOPS_PER_PAIR = 8 + 16 + 1 + 11 + 2
 # for a 256 MiB device copy (FETCH 0.5x, WRITE 1.0x of the bytes moved).  Keyed
 # by the SHA-256 of the kernel sources: a changed kernel reports null.
 TRAFFIC_SOURCES = ("paper_2106_15508_amd/csrc/smc.hip", "paper_2106_15508_amd/csrc/dmath.h",
-                   "paper_2106_15508_amd/csrc/kernels.h")
+                   "paper_2106_15508_amd/csrc/kernels.h", "paper_2106_15508_amd/csrc/wterm.h",
+                   "paper_2106_15508_amd/csrc/sim.hip", "paper_2106_15508_amd/csrc/propose.h")
 TRAFFIC_MEASURED = {
-    # weights_kernel (windowed), c2: FETCH_SIZE 116340 KiB x 2 + WRITE_SIZE 33355 KiB x 1 per launch
-    ("063017602bdcc342", "c2", "weights_kernel"): 116340 * 1024 * 2 + 33355 * 1024,
+    # c2, per launch: FETCH_SIZE KiB x 2 + WRITE_SIZE KiB x 1
+    ("44992cb41fc0c7f8", "c2", "weights_kernel"): 167219 * 1024 * 2 + 30224 * 1024,
+    ("44992cb41fc0c7f8", "c2", "propose_kernel"): 18855 * 1024 * 2 + 21349 * 1024,
 }
 # FP64 flops of one simulated proposal-day with all five transitions in the
 # normal branch of the binomial draw: state sums 2, g (log 34, exp 33, 4) 71,
@@ -199,7 +201,8 @@ def bench_batched(args):
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
                      "kernel": "whole batched stage (graph replay; bweights_kernel and propose_persistent_kernel "
-                               "dominate), evaluated weight terms x 45 + proposal-days x 590 flops",
+                               f"dominate), evaluated weight terms x {FLOPS_PER_PAIR} + proposal-days x "
+                               f"{FLOPS_PER_DAY} flops",
                      "avg_launch_ms": round(sec * 1e3 / R, 3), "launches": R},
     }
     del ws_tensor

@@ -127,8 +127,8 @@ typedef struct {
     int64_t n_k_propose;          /* proposal kernel launches (= batches) */
     int64_t sim_days;             /* proposal-days simulated (early exit stops counting) */
     int64_t weight_pairs;         /* N x survivors terms of the importance-weight sums */
-    int64_t weight_terms;         /* terms actually evaluated (the rest lie outside every window and
-                                     are exactly zero) */
+    int64_t weight_terms;         /* terms actually evaluated (the rest lie outside every window: their
+                                     exponents are below -708 and cannot change a sum) */
     double mcmc_s;                /* STEP_MCMC: step size after this stage (0 otherwise) */
     double beta_b_real;           /* Beta shape b as a real number (STEP_MEANVAR / STEP_MODECONC) */
 } abcsmc_round_info;

@@ -244,10 +244,12 @@ using wterm::wave_max;
 using wterm::wave_min;
 
 // ---- windowed evaluation -------------------------------------------------
-// A term is exactly zero (exponent below -708) once |u_jd - u_kd| exceeds
-// sqrt(1416) sigma_j in any one coordinate d; with R_j = 37.7 sigma_j (0.4%
-// above that bound) every column outside [u_jd - R_j, u_jd + R_j] contributes
-// exactly 0, in the oracle's sum as here.  Per stage: pick the coordinate d*
+// A term's exponent is below -708 once |u_jd - u_kd| exceeds sqrt(1416)
+// sigma_j in any one coordinate d; with R_j = 37.7 sigma_j (0.4% above that
+// bound) every column outside [u_jd - R_j, u_jd + R_j] contributes exactly 0
+// to the oracle's sum and at most a subnormal-size value to the kernel's,
+// which cannot change a row sum (each row holds its parent's term, at least
+// e^-185), so skipping them changes nothing.  Per stage: pick the coordinate d*
 // with the largest spread among the columns (the window then excludes the
 // most columns: sigma is the same in every coordinate), sort the columns by it, sort
 // the rows by (octave of sigma, u_d*), and let every workgroup (256

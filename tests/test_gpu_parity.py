@@ -227,3 +227,58 @@ def test_alternative_beta_parameterisations_bitwise(oracle, wl):
     _compare_run(oracle, wl, ref, infos, pops, wl.n_rounds)
     for i in range(1, wl.n_rounds):
         assert _bits([infos[i]["beta_b_real"]])[0] == _bits([ref.beta_b_real[i]])[0], i
+
+
+@pytest.mark.parametrize("wl", [
+    # smallest population of particles, one simulated day
+    W.tiny(n_particles=2, n_days=1, n_rounds=4, seed=21),
+    # degenerate prior box: three parameters fixed (lo = hi)
+    W.tiny(lo=(0.3, 1.0, 0.5, 0.0, 0.1, 0.0, 0.2, 0.0), hi=(0.3, 100.0, 0.5, 1.0, 0.1, 0.5, 0.2, 2.0),
+           n_rounds=3, seed=22),
+    # tiny survival ratio (eq. 8 at the 2nd order statistic) and N not a multiple of a wave
+    W.tiny(n_particles=97, surv_ratio=0.01, n_rounds=4, seed=23),
+])
+def test_edge_configurations_bitwise(oracle, wl):
+    obs = oracle.observations(wl)
+    ref = oracle.run(wl, obs)
+    assert ref.rc == 0
+    infos, pops = _gpu_run(wl, obs, wl.n_rounds, flags=A.F_EARLY_EXIT)
+    _compare_run(oracle, wl, ref, infos, pops, wl.n_rounds)
+
+
+def test_predict_shorter_than_fitted_horizon(oracle):
+    wl = W.tiny(n_rounds=2)
+    obs = oracle.observations(wl)
+    ref = oracle.run(wl, obs)
+    want = oracle.predict(wl, obs, ref.u[-1], 5, seed=3, quantiles=(0.5,))
+    with A.Context(wl, obs) as ctx:
+        ctx.run(2)
+        got = ctx.predict(5, seed=3, quantiles=(0.5,))
+        with pytest.raises(A.AbcsmcError):
+            ctx.predict(0, seed=3, quantiles=(0.5,))
+        with pytest.raises(A.AbcsmcError):
+            ctx.predict(5, seed=3, quantiles=(1.5,))
+    assert np.array_equal(_bits(got), _bits(want))
+
+
+def test_mcmc_budget_error_leaves_context_usable(oracle):
+    """A stage that cannot reach N acceptances within max_proposals returns
+    EBUDGET and leaves the last completed stage in place."""
+    wl = W.tiny(step_schedule=W.STEP_MCMC, batch=64, mcmc_s0=0.1, mcmc_tune=3, max_proposals=320, seed=24)
+    obs = oracle.observations(wl)
+    with A.Context(wl, obs) as ctx:
+        ctx.round()
+        before = ctx.population()
+        done = 1
+        for _ in range(6):
+            try:
+                ctx.round()
+                done += 1
+            except A.AbcsmcError as e:
+                assert e.code == A.EBUDGET
+                break
+        else:
+            pytest.skip("budget never reached for this seed")
+        assert ctx.rounds_done() == done
+        if done == 1:
+            assert np.array_equal(ctx.population()["index"], before["index"])

@@ -46,10 +46,11 @@ void launch_gemm(const GemmArgs& g, float* part, hipStream_t s);
 void launch_colsum(const float* X, int M, int N, int ld, float* out, float* part, hipStream_t s);
 void launch_mse_grad(const float* out, const float* y, int n, float* dout, float* se, hipStream_t s);
 void launch_adam(float* w, const float* g, float* m, float* v, int n, float lr, int step, hipStream_t s);
-void launch_score(const float* out, int n, double* score, hipStream_t s);
 void mlp_forward(const float* params, const float* x, int n, MlpActs& s, hipStream_t st);
-// Forward only (no pre-activations kept): hA, hB n x 256 scratch, out n x 3.
-void mlp_infer(const float* params, const float* x, int n, float* hA, float* hB, float* out, hipStream_t st);
+// Forward only, one fused kernel (activations in LDS): wb receives the bf16
+// copy of the parameters (kMlpParams); out n x 3 and/or score n (predicted
+// squared distance sum_c expm1(y_c)^2), either may be null.
+void mlp_infer(const float* params, __bf16* wb, const float* x, int64_t n, float* out, double* score, hipStream_t st);
 void mlp_backward(const float* params, const float* x, int n, MlpActs& s, const float* dout, float* grad,
                   hipStream_t st);
 

@@ -234,18 +234,147 @@ __global__ __launch_bounds__(256) void adam_kernel(float* w, const float* gr, fl
     w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// score = sum_c expm1(yhat_c)^2: the predicted squared distance (targets are log1p of the
-// three per-series distances).
-__global__ __launch_bounds__(256) void score_kernel(const float* out, int n, double* score)
+// ---------------------------------------------------------------------------
+// Fused inference (scoring): one workgroup carries 128 rows through all four
+// layers.  The activations stay in LDS as bf16 ([128][264], 16-byte row skew);
+// the weights are read as bf16 from global memory (they stay in L2).  Wave w
+// computes output columns [64w, 64w + 64) of each 256-wide layer for all 128
+// rows (8 x 4 blocks of 16 x 16, v_mfma_f32_16x16x32_bf16); layer 1's K = 8 and
+// layer 4's N = 3 are zero-padded to the instruction's 32 and 16.  Rounding
+// points are those of the per-layer products: bf16 operands, fp32 sums, bias
+// and GELU in fp32, the activation rounded to bf16 for the next layer.  The
+// score is sum_c expm1(yhat_c)^2, the predicted squared distance (the targets
+// are log1p of the three per-series distances); NaN and overflow rank last.
+constexpr int kFR = 128;       // rows per workgroup
+constexpr int kHP = kH + 8;    // LDS row pitch (bf16) of the activations
+constexpr int kOffB1 = kH * kIn, kOffW2 = kOffB1 + kH, kOffB2 = kOffW2 + kH * kH, kOffW3 = kOffB2 + kH,
+              kOffB3 = kOffW3 + kH * kH, kOffW4 = kOffB3 + kH, kOffB4 = kOffW4 + kOut * kH;
+
+__global__ __launch_bounds__(256) void to_bf16_kernel(const float* __restrict__ p, __bf16* __restrict__ q, int n)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    for (int c = 0; c < 3; ++c) {
-        const double e = expm1((double)out[i * 3 + c]);
-        s += e * e;
+    if (i < n) q[i] = to_bf16(p[i]);
+}
+
+// acc + bias, GELU, bf16 into H (rows 16a + 4(lane/16) + e, column n0 + 16b + lane%16)
+__device__ __forceinline__ void fused_epilogue(f32x4 (&acc)[8][4], const float* __restrict__ bias, int n0, int lane,
+                                               __bf16 (*H)[kHP])
+{
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int c = n0 + 16 * b + lane % 16;
+        const float bc = bias[c];
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) H[16 * a + 4 * (lane / 16) + e][c] = to_bf16(gelu_f(acc[a][b][e] + bc));
     }
-    score[i] = s <= 1.0e300 ? s : __builtin_inf();  // NaN and overflow rank last
+}
+
+__global__ __launch_bounds__(256) void mlp_fused_kernel(const float* __restrict__ params, const __bf16* __restrict__ wb,
+                                                        const float* __restrict__ x, int64_t n, float* out,
+                                                        double* score)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 H[kFR][kHP];
+    __shared__ __attribute__((aligned(16))) __bf16 X0[kFR][kLdsK];
+    __shared__ float O[kFR][4];
+    const int t = threadIdx.x, wave = t / 64, lane = t % 64;
+    const int64_t r0 = (int64_t)blockIdx.x * kFR;
+    const int n0 = 64 * wave;
+    const bf16x8 zero8 = {};
+    // inputs as bf16, K padded to 32
+    for (int i = t; i < kFR * kTK; i += 256) {
+        const int r = i / kTK, k = i % kTK;
+        float v = 0.f;
+        if (k < kIn && r0 + r < n) v = x[(r0 + r) * kIn + k];
+        X0[r][k] = to_bf16(v);
+    }
+    __syncthreads();
+    f32x4 acc[8][4];
+    // layer 1 (8 -> 256): one K step
+    {
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        bf16x8 bfr[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int c = n0 + 16 * b + lane % 16;
+            bfr[b] = lane / 16 == 0 ? *reinterpret_cast<const bf16x8*>(wb + (size_t)c * kIn) : zero8;
+        }
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const bf16x8 af = *reinterpret_cast<const bf16x8*>(&X0[16 * a + lane % 16][8 * (lane / 16)]);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[b], acc[a][b], 0, 0, 0);
+        }
+        fused_epilogue(acc, params + kOffB1, n0, lane, H);
+    }
+    __syncthreads();
+    // layers 2 and 3 (256 -> 256)
+    for (int L = 0; L < 2; ++L) {
+        const __bf16* W = wb + (L == 0 ? kOffW2 : kOffW3);
+        const float* bias = params + (L == 0 ? kOffB2 : kOffB3);
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < kH; k0 += kTK) {
+            bf16x8 bfr[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int c = n0 + 16 * b + lane % 16;
+                bfr[b] = *reinterpret_cast<const bf16x8*>(W + (size_t)c * kH + k0 + 8 * (lane / 16));
+            }
+#pragma unroll
+            for (int a = 0; a < 8; ++a) {
+                const bf16x8 af = *reinterpret_cast<const bf16x8*>(&H[16 * a + lane % 16][k0 + 8 * (lane / 16)]);
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[b], acc[a][b], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // every wave has read H
+        fused_epilogue(acc, bias, n0, lane, H);
+        __syncthreads();
+    }
+    // layer 4 (256 -> 3, N padded to 16): wave w takes rows [32w, 32w + 32)
+    {
+        f32x4 o[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+        const int c = lane % 16;
+        for (int k0 = 0; k0 < kH; k0 += kTK) {
+            const bf16x8 bfr = c < kOut ? *reinterpret_cast<const bf16x8*>(wb + kOffW4 + (size_t)c * kH + k0 + 8 * (lane / 16))
+                                        : zero8;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const bf16x8 af =
+                    *reinterpret_cast<const bf16x8*>(&H[32 * wave + 16 * a + lane % 16][k0 + 8 * (lane / 16)]);
+                o[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr, o[a], 0, 0, 0);
+            }
+        }
+        if (c < kOut) {
+            const float bc = params[kOffB4 + c];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) O[32 * wave + 16 * a + 4 * (lane / 16) + e][c] = o[a][e] + bc;
+        }
+    }
+    __syncthreads();
+    if (t < kFR && r0 + t < n) {
+        const int64_t row = r0 + t;
+        if (out)
+            for (int c = 0; c < kOut; ++c) out[row * kOut + c] = O[t][c];
+        if (score) {
+            double sc = 0.0;
+            for (int c = 0; c < kOut; ++c) {
+                const double e = expm1((double)O[t][c]);
+                sc += e * e;
+            }
+            score[row] = sc <= 1.0e300 ? sc : __builtin_inf();
+        }
+    }
 }
 
 }  // namespace
@@ -297,10 +426,6 @@ void launch_adam(float* w, const float* g, float* m, float* v, int n, float lr, 
     hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w, g, m, v, n, lr, b1, b2, 1e-8f, c1, c2);
 }
 
-void launch_score(const float* out, int n, double* score, hipStream_t s)
-{
-    hipLaunchKernelGGL(score_kernel, dim3((n + 255) / 256), dim3(256), 0, s, out, n, score);
-}
 
 // ---------------------------------------------------------------------------
 // Network passes built from the GEMM.  Parameters, flat FP32:
@@ -363,24 +488,12 @@ void mlp_forward(const float* params, const float* x, int n, MlpActs& s, hipStre
     launch_gemm(g, nullptr, st);
 }
 
-void mlp_infer(const float* params, const float* x, int n, float* hA, float* hB, float* out, hipStream_t st)
+void mlp_infer(const float* params, __bf16* wb, const float* x, int64_t n, float* out, double* score, hipStream_t st)
 {
-    MlpView w = mlp_view(const_cast<float*>(params));
-    GemmArgs g = gemm(x, kIn, false, w.W1, kIn, true, hA, kH, n, kH, kIn);
-    g.bias = w.b1;
-    g.epi = kGelu;
-    launch_gemm(g, nullptr, st);
-    g = gemm(hA, kH, false, w.W2, kH, true, hB, kH, n, kH, kH);
-    g.bias = w.b2;
-    g.epi = kGelu;
-    launch_gemm(g, nullptr, st);
-    g = gemm(hB, kH, false, w.W3, kH, true, hA, kH, n, kH, kH);
-    g.bias = w.b3;
-    g.epi = kGelu;
-    launch_gemm(g, nullptr, st);
-    g = gemm(hA, kH, false, w.W4, kH, true, out, kOut, n, kOut, kH);
-    g.bias = w.b4;
-    launch_gemm(g, nullptr, st);
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, params, wb, kMlpParams);
+    if (n > 0)
+        hipLaunchKernelGGL(mlp_fused_kernel, dim3((unsigned)((n + kFR - 1) / kFR)), dim3(256), 0, st, params,
+                           (const __bf16*)wb, x, n, out, score);
 }
 
 // Backward from dout (n x 3) to the flat gradient (same layout as params).

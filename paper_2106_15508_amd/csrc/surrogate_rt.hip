@@ -21,7 +21,7 @@ using namespace abcsmc::rt;
 namespace abcsmc {
 namespace rt {
 
-constexpr int64_t kInferRows = 65536;  // network rows per inference chunk
+constexpr int64_t kInferRows = 65536;  // rows per call of the network hooks
 constexpr int64_t kPoolMax = (int64_t)1 << 22;
 constexpr int32_t kTrainBatchMax = 16384;
 
@@ -44,7 +44,8 @@ struct Surrogate {
     int64_t n_train = 0;
     double *pu = nullptr, *psigma = nullptr, *score = nullptr, *kd = nullptr;
     int32_t *pparent = nullptr, *patt = nullptr;
-    float *px = nullptr, *pout = nullptr, *hA = nullptr, *hB = nullptr;
+    float* px = nullptr;
+    __bf16* wb = nullptr;                                    // bf16 copy of the network for scoring
     unsigned char* paudit = nullptr;
     uint32_t* kept = nullptr;
     unsigned long long *mask_pool = nullptr, *mask_kept = nullptr, *totals = nullptr;
@@ -172,10 +173,7 @@ size_t carve_surrogate(Surrogate& S, char* base, int64_t N)
     S.pparent = c.take<int32_t>((size_t)P);
     S.patt = c.take<int32_t>((size_t)P);
     S.px = c.take<float>((size_t)P * kIn);
-    S.pout = c.take<float>((size_t)P * kOut);
-    const int64_t rows = std::min<int64_t>(P, kInferRows);
-    S.hA = c.take<float>((size_t)rows * kH);
-    S.hB = c.take<float>((size_t)rows * kH);
+    S.wb = c.take<__bf16>((size_t)kMlpParams);
     S.paudit = c.take<unsigned char>((size_t)P);
     S.kept = c.take<uint32_t>((size_t)P);
     S.mask_pool = c.take<unsigned long long>((size_t)P / kWave + 4);
@@ -294,10 +292,7 @@ int surrogate_batches(abcsmc_ctx* x, const ProposeArgs& pa, const DevPop& dst, i
         qa.base = (uint32_t)base;
         qa.count = (uint32_t)B;
         launch_perturb_only(qa, s);
-        for (int64_t r0 = 0; r0 < B; r0 += kInferRows)
-            mlp_infer(S.tr.params, S.px + r0 * kIn, (int)std::min<int64_t>(kInferRows, B - r0), S.hA, S.hB,
-                      S.pout + r0 * kOut, s);
-        launch_score(S.pout, (int)B, S.score, s);
+        mlp_infer(S.tr.params, S.wb, S.px, B, nullptr, S.score, s);
         if (batches == 0) {
             // tau: keep_frac percentile of the stage's first batch of scores
             SelectArgs ta{S.score, (int32_t)B, S.cfg.keep_frac, x->scratch(), S.tau};
@@ -599,9 +594,8 @@ int abcsmc_mlp_forward(const float* params, int64_t n, const float* xs, float* o
     Carver c{nullptr};
     for (int pass = 0; pass < 2; ++pass) {
         float* P = c.take<float>(kMlpParams);
+        __bf16* Wb = c.take<__bf16>(kMlpParams);
         float* X = c.take<float>((size_t)n * kIn);
-        float* hA = c.take<float>((size_t)n * kH);
-        float* hB = c.take<float>((size_t)n * kH);
         float* O = c.take<float>((size_t)n * kOut);
         if (pass == 0) {
             HOOKCHK(hipMalloc(&m.p, c.off));
@@ -610,7 +604,7 @@ int abcsmc_mlp_forward(const float* params, int64_t n, const float* xs, float* o
         }
         HOOKCHK(hipMemcpy(P, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice));
         HOOKCHK(hipMemcpy(X, xs, (size_t)n * kIn * sizeof(float), hipMemcpyHostToDevice));
-        mlp_infer(P, X, (int)n, hA, hB, O, nullptr);
+        mlp_infer(P, Wb, X, n, O, nullptr, nullptr);
         HOOKCHK(hipGetLastError());
         HOOKCHK(hipMemcpy(out, O, (size_t)n * kOut * sizeof(float), hipMemcpyDeviceToHost));
     }

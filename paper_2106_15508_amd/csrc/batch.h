@@ -98,6 +98,7 @@ struct BatchArgs {
     unsigned long long* rowkeys;  // npad: (run, sigma octave, row key, row) sorted
     double* scols;             // n_total x 9 sorted columns (u_k, q_k)
     double* skey;              // n_total sorted sort-coordinate values
+    double* rwin;              // n_total per-row window half-widths (slot off_r + j)
     int2* win;                 // per 256-row block: column window [x, y) within the run
     size_t npad;               // power-of-two sort length >= n_total
     int32_t n_total;           // sum of N_r

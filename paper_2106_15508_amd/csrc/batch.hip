@@ -429,12 +429,12 @@ __global__ __launch_bounds__(kBlock) void bcompact_scatter_kernel(BatchArgs a)
 
 // Weight window, per run (as the single-run pass): the sort coordinate d* of
 // largest column variance; columns sorted by (run, u_{k,d*}); rows sorted by
-// (run, sigma octave, u_{j,d*}); each 256-row block gets the column range
-// |u_{k,d*} - u_{j,d*}| <= kWindow sigma_j of its rows.  One batch-wide bitonic
+// (run, sigma octave, u_{j,d*}); each row's half-width comes from its parent's
+// term (wterm::window_halfwidth) and each 256-row block gets the union of its
+// rows' column ranges.  One batch-wide bitonic
 // sort per key set: the run index in the top 12 bits keeps every run's keys in
 // its own slot range [off_r, off_r + N_r).
 using wterm::coord_key32;
-using wterm::kWindow;
 using wterm::lower_index;
 using wterm::sigma_octave;
 using wterm::wave_max;
@@ -506,6 +506,11 @@ __global__ __launch_bounds__(kBlock) void bkeys_kernel(BatchArgs a)
                        : run | (0xFFFFFFFFull << 20) | k;
     const int nx = S.nxt;
     a.rowkeys[i] = run | (sigma_octave(R.sigma[nx][k]) << 46) | ((coord_key32(R.u[nx][k * kNP + ds]) >> 6) << 20) | k;
+    const double* uj = R.u[nx] + k * kNP;
+    const int32_t par = R.parent[nx][k];
+    const bool ok = par >= 0 && par < R.N;
+    a.rwin[i] = wterm::window_halfwidth(uj, R.sigma[nx][k], ok ? R.u[1 - nx] + (size_t)par * kNP : uj,
+                                        ok ? (double)R.q[par] : 0.0, (double)R.cdf[R.N - 1]);
 }
 
 __global__ __launch_bounds__(kBlock) void bcolgather_kernel(BatchArgs a)
@@ -537,7 +542,7 @@ __global__ __launch_bounds__(kBlock) void bwindow_kernel(BatchArgs a)
     double lo = __builtin_inf(), hi = -__builtin_inf();
     if (rr < R.N) {
         const size_t j = (size_t)(a.rowkeys[R.off + rr] & 0xFFFFFull);
-        const double W = kWindow * R.sigma[nx][j];
+        const double W = a.rwin[R.off + j];
         const double x = R.u[nx][j * kNP + S.dstar];
         lo = x - W;
         hi = x + W;
@@ -592,8 +597,8 @@ __global__ __launch_bounds__(kBlock) void bweights_kernel(BatchArgs a)
         for (int d = 0; d < kNP; ++d) uj[d] = R.u[nx][j * kNP + d];
         const double sj = R.sigma[nx][j];
         cj = wterm::row_scale(sj, a.ex);
-        lo = uj[ds] - kWindow * sj;
-        hi = uj[ds] + kWindow * sj;
+        lo = uj[ds] - a.rwin[R.off + j];
+        hi = uj[ds] + a.rwin[R.off + j];
     } else {
 #pragma unroll
         for (int d = 0; d < kNP; ++d) uj[d] = 0.0;

@@ -96,7 +96,7 @@ RunLayout run_layout(const abcsmc_config& c, size_t o)
 // (power-of-two length), sorted columns, their sort-coordinate values, and
 // one window per 256-row block.
 struct WinLayout {
-    size_t colkeys, rowkeys, scols, skey, win, end, npad;
+    size_t colkeys, rowkeys, scols, skey, rwin, win, end, npad;
 };
 
 WinLayout win_layout(size_t o, size_t n_total, size_t n_fin)
@@ -112,6 +112,7 @@ WinLayout win_layout(size_t o, size_t n_total, size_t n_fin)
     L.rowkeys = take(L.npad * 8);
     L.scols = take(n_total * 9 * 8);
     L.skey = take(n_total * 8);
+    L.rwin = take(n_total * 8);
     L.win = take(n_fin * sizeof(int2));
     L.end = o;
     return L;
@@ -494,6 +495,7 @@ int abcsmc_batch_init(const abcsmc_config* cfgs, int32_t n_runs, const int64_t* 
     A.rowkeys = (unsigned long long*)(b->ws + WL.rowkeys);
     A.scols = (double*)(b->ws + WL.scols);
     A.skey = (double*)(b->ws + WL.skey);
+    A.rwin = (double*)(b->ws + WL.rwin);
     A.win = (int2*)(b->ws + WL.win);
     A.npad = WL.npad;
     A.n_total = (int32_t)n_total;

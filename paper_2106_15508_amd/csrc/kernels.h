@@ -136,8 +136,15 @@ struct WeightArgs {
     int2* win;              // per row block: sorted column range [first, end) of its window
     int32_t cols_per_chunk; // columns per grid-y chunk of a window
     unsigned long long* terms;  // device counter of evaluated terms
-    // exp by table: 64/ln2, ln2/64 (hi, lo), Taylor 1/2!, 1/3!, 1/4!, 1/5! (kernel
-    // arguments so they sit in scalar registers)
+    // per-row window half-widths from each row's parent term
+    const int32_t* parent;  // N parent indices into the previous population
+    const double* u_prev;   // previous population, n_prev x 8
+    const uint64_t* q_prev; // its resampling weights q_k (0 for non-survivors)
+    const uint64_t* cdf;    // its integer CDF (cdf[n_prev - 1] = Q)
+    int32_t n_prev;
+    double* rwin;           // N half-widths W_j sigma_j
+    // table exponential: ln2/1024, its square / 2, its cube / 6, 1024/ln2
+    // (kernel arguments so they sit in scalar registers)
     double ex[7];
 };
 

@@ -85,6 +85,7 @@ Layout make_layout(const abcsmc_config& c)
     L.dimpart = take(256 * 16 * sizeof(double));
     L.dstar = take(sizeof(int32_t));
     L.win = take(((N + kBlock - 1) / kBlock) * sizeof(int2));
+    L.rwin = take(N * sizeof(double));
     L.total = o;
     return L;
 }
@@ -474,6 +475,12 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
         wa.dimpart = x->at<double>(x->L.dimpart);
         wa.dstar = x->at<int32_t>(x->L.dstar);
         wa.npad = sort_padded_size((size_t)N);
+        wa.parent = dst.parent;
+        wa.u_prev = prev.u;
+        wa.q_prev = x->at<uint64_t>(x->L.q);
+        wa.cdf = x->at<uint64_t>(x->L.cdf);
+        wa.n_prev = N;
+        wa.rwin = x->at<double>(x->L.rwin);
         weight_exp_constants(wa.ex);
         HIPCHK(x, hipEventRecord(x->ev[7], s));
         launch_weights(wa, s);

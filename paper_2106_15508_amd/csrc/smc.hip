@@ -223,38 +223,33 @@ __global__ __launch_bounds__(kBlock) void resample_write_kernel(ResampleArgs a)
 //   l_j = 8 log sigma_j - log L_j,
 // the log of 1 / (proposal density at u_j given sigma_j) up to a constant
 // (prior density 1 on the cube).  One lane per row; the columns are split in
-// `chunks` contiguous ranges (grid y) so the launch fills the chip; tiles of
-// (u_k, q_k) stream through LDS and every lane of the wave reads the same
-// column (broadcast).  Terms whose exponent is below -708 are exactly 0 and
-// skipped (a wave skips the exponential when all its lanes do).  Two columns
-// are evaluated per iteration into independent accumulators; per-tile and
-// per-chunk partial sums are added in a fixed order.
+// `chunks` contiguous ranges (grid y) so the launch fills the chip; every lane
+// of a wave reads the same column through scalar loads.  Four columns are
+// evaluated per step into even/odd partial sums; per-chunk partial sums are
+// added in a fixed order.
 //
-// The exponential here is table driven: x = (64 k + i) ln2/64 + r with
-// |r| <= ln2/128, exp(x) = 2^k 2^(i/64) (1 + r + r^2/2 + ... + r^5/5!).  Its
-// relative error (a few 1e-16) is far inside the 1e-12 the weights are held
-// to; the trajectories never use it.
+// The exponential here is table driven (1024 entries of 2^(i/1024) in LDS and
+// a cubic in the remainder).  Its relative error (a few 1e-16) is far inside
+// the 1e-12 the weights are held to; the trajectories never use it.
 // ---------------------------------------------------------------------------
 using wterm::kTile;
 using wterm::coord_key32;
-using wterm::kWindow;
 using wterm::lower_index;
 using wterm::sigma_octave;
 using wterm::wave_max;
 using wterm::wave_min;
 
 // ---- windowed evaluation -------------------------------------------------
-// A term's exponent is below -708 once |u_jd - u_kd| exceeds sqrt(1416)
-// sigma_j in any one coordinate d; with R_j = 37.7 sigma_j (0.4% above that
-// bound) every column outside [u_jd - R_j, u_jd + R_j] contributes exactly 0
-// to the oracle's sum and at most a subnormal-size value to the kernel's,
-// which cannot change a row sum (each row holds its parent's term, at least
-// e^-185), so skipping them changes nothing.  Per stage: pick the coordinate d*
-// with the largest spread among the columns (the window then excludes the
-// most columns: sigma is the same in every coordinate), sort the columns by it, sort
-// the rows by (octave of sigma, u_d*), and let every workgroup (256
-// consecutive sorted rows) visit only its window of sorted columns; a wave
-// also skips tiles outside its own window.
+// Row j only needs the columns whose coordinate d* lies within its
+// half-width R_j = W_j sigma_j of u_jd*: every other column has a term at
+// most q_k e^{-W_j^2/2}, and W_j is chosen from the row's own parent term so
+// that all of them together stay below 2^-64 of the row sum (at most 37.7,
+// where every omitted exponential is below e^-710).  Per stage: pick the
+// coordinate d* with the largest spread among the columns (the windows then
+// exclude the most columns: sigma is the same in every coordinate), sort the
+// columns by it, sort the rows by (octave of sigma, u_d*), and let every
+// workgroup (256 consecutive sorted rows) visit only the union of its rows'
+// windows; a wave also skips tiles outside its own lanes' union.
 
 constexpr int kDimBlocks = 256;
 
@@ -336,6 +331,13 @@ __global__ __launch_bounds__(kBlock) void wrowkeys_kernel(WeightArgs a)
     const int ds = *a.dstar;
     const unsigned long long hi = (sigma_octave(a.sigma[i]) << 26) | (coord_key32(a.u[i * kNP + ds]) >> 6);
     a.rowkeys[i] = (hi << 32) | (unsigned long long)i;
+    double uj[kNP];
+#pragma unroll
+    for (int d = 0; d < kNP; ++d) uj[d] = a.u[i * kNP + d];
+    const int32_t par = a.parent[i];
+    const bool ok = par >= 0 && par < a.n_prev;
+    a.rwin[i] = wterm::window_halfwidth(uj, a.sigma[i], ok ? a.u_prev + (size_t)par * kNP : uj,
+                                        ok ? (double)a.q_prev[par] : 0.0, (double)a.cdf[a.n_prev - 1]);
 }
 
 // Window of each row block (256 consecutive sorted rows): the sorted column
@@ -348,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void wwindow_kernel(WeightArgs a)
     double lo = __builtin_inf(), hi = -__builtin_inf();
     if (r < a.N) {
         const size_t j = (size_t)(a.rowkeys[r] & 0xFFFFFFFFull);
-        const double R = kWindow * a.sigma[j];
+        const double R = a.rwin[j];
         const double x = a.u[j * kNP + ds];
         lo = x - R;
         hi = x + R;
@@ -398,7 +400,7 @@ __global__ __launch_bounds__(kBlock) void weights_kernel(WeightArgs a)
         for (int d = 0; d < kNP; ++d) uj[d] = a.u[j * kNP + d];
         const double sj = a.sigma[j];
         cj = wterm::row_scale(sj, a.ex);
-        const double R = kWindow * sj;
+        const double R = a.rwin[j];
         lo = uj[ds] - R;
         hi = uj[ds] + R;
     } else {

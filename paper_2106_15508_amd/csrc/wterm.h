@@ -121,6 +121,35 @@ __device__ __forceinline__ double row_sum(const double* uj, double cj, const_col
 // exactly 0, so it can be skipped without changing the sum.
 constexpr double kWindow = 37.7;
 
+// Narrower per-row window with a bound on what it leaves out.  Every column
+// outside |u_kd - u_jd| <= W sigma_j (any one coordinate d) has a term at most
+// q_k e^{-W^2/2}, so all of them together are at most Q e^{-W^2/2}
+// (Q = sum_k q_k).  The row sum holds the parent's own term
+// L_par = q_par e^{-|u_j - u_par|^2 / (2 sigma_j^2)}, so with
+//   W^2 = 2 (ln Q - ln L_par + 64 ln 2)
+// the omitted mass is at most 2^-64 of the row sum -- below the rounding of
+// the sum itself.  The parent always lies inside (W^2 >= |u_j - u_par|^2 /
+// sigma_j^2 because Q >= q_par).  The result is capped at kWindow; a missing
+// or zero parent weight leaves kWindow.  Returns the half-width W sigma_j.
+__device__ __forceinline__ double window_halfwidth(const double* uj, double sj, const double* up, double qpar,
+                                                   double Q)
+{
+    double W = kWindow;
+    if (qpar > 0.0 && Q >= qpar && sj > 0.0) {
+        double d2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < kNP; ++d) {
+            const double e = uj[d] - up[d];
+            d2 = d2 + e * e;
+        }
+        const double x = d2 / (2.0 * sj * sj);
+        const double w2 = 2.0 * ((dm::log(Q) - dm::log(qpar)) + x + 64.0 * 0.6931471805599453);
+        const double w = __builtin_sqrt(w2);
+        if (w < W) W = w;
+    }
+    return W * sj;
+}
+
 // 32-bit monotone key of a unit-cube coordinate (truncation: keys tie within
 // 2.4e-10, far below the window margin 0.07 sigma >= 7e-10).
 __device__ __forceinline__ unsigned long long coord_key32(double u)

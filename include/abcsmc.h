@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define ABCSMC_ABI_VERSION 2
+#define ABCSMC_ABI_VERSION 3
 #define ABCSMC_NPAR 8
 
 enum {
@@ -75,7 +75,10 @@ enum {
 enum {
     ABCSMC_F_EARLY_EXIT = 1,      /* stop simulating a proposal once its partial distance exceeds eps
                                      (acceptances unchanged; rejected proposals report d = +inf) */
-    ABCSMC_F_STEP_IS_VARIANCE = 2 /* eq. 12 calls s a variance: perturb with sigma = sqrt(s) */
+    ABCSMC_F_STEP_IS_VARIANCE = 2, /* eq. 12 calls s a variance: perturb with sigma = sqrt(s) */
+    ABCSMC_F_SKIP_WEIGHTS = 4      /* no importance weights: every stage reports W = 1/N, log-weights 0
+                                      and ESS = N (simulation-only runs; trajectories, acceptances and
+                                      tolerances never depend on the weights) */
 };
 
 /*
@@ -106,6 +109,11 @@ typedef struct {
     size_t workspace_bytes;       /* its size; see abcsmc_workspace_size */
     double mcmc_s0;               /* STEP_MCMC: initial step size s > 0 */
     int32_t mcmc_tune;            /* STEP_MCMC: number of tuned batches (>= 0) */
+    int32_t n_eps_schedule;       /* 0..4096 tolerances to replay (single-run contexts only) */
+    const double* eps_schedule;   /* host array (copied at init): stage i = 1..n_eps_schedule accepts
+                                     against eps_schedule[i-1] (finite, >= 0) instead of eq. 8's
+                                     percentile of stage i-1; later stages use eq. 8 again.  eq. 16's
+                                     eps_1 is then eps_schedule[0].  NULL when n_eps_schedule = 0 */
 } abcsmc_config;
 
 typedef struct {
@@ -127,8 +135,8 @@ typedef struct {
     int64_t n_k_propose;          /* proposal kernel launches (= batches) */
     int64_t sim_days;             /* proposal-days simulated (early exit stops counting) */
     int64_t weight_pairs;         /* N x survivors terms of the importance-weight sums */
-    int64_t weight_terms;         /* terms actually evaluated (the rest lie outside every window: their
-                                     exponents are below -708 and cannot change a sum) */
+    int64_t weight_terms;         /* terms actually evaluated (the rest lie outside every row's window,
+                                     which bounds their total by 2^-64 of the row sum) */
     double mcmc_s;                /* STEP_MCMC: step size after this stage (0 otherwise) */
     double beta_b_real;           /* Beta shape b as a real number (STEP_MEANVAR / STEP_MODECONC) */
 } abcsmc_round_info;
@@ -184,6 +192,23 @@ int abcsmc_reset(abcsmc_ctx* ctx);
 
 /* Stages completed so far. */
 int abcsmc_rounds_done(const abcsmc_ctx* ctx);
+
+/* Checkpoint and resume.  A snapshot holds what the next stage reads from
+ * the last completed one: the population (u, d, sigma, parent, index,
+ * attempts, log-weights, weights; eqs. 9-11 resample it), the stage count,
+ * eps^{i+1} (eq. 8) and eps_1 (eq. 16), the batch-sizing rate and the MCMC
+ * step-size state, plus a fingerprint of the configuration and the
+ * observations.  abcsmc_snapshot with buf == NULL stores the size in *bytes;
+ * otherwise *bytes is the capacity of buf (host memory, caller-owned) and is
+ * set to the bytes written (EINVAL if too small).  ESTATE before the first
+ * stage or while the learned screen is enabled.
+ * abcsmc_restore creates a context as abcsmc_init(cfg, obs) does and loads
+ * the snapshot; EINVAL if the buffer is malformed or was taken under another
+ * configuration (seed, sizes, model, schedule) or other observations.  The
+ * restored context continues the run bit for bit (its own abcsmc_reset goes
+ * back to stage 0). */
+int abcsmc_snapshot(const abcsmc_ctx* ctx, void* buf, size_t* bytes);
+int abcsmc_restore(const abcsmc_config* cfg, const int64_t* obs, const void* buf, size_t bytes, abcsmc_ctx** out);
 
 /* init + n_rounds x round + weights + free.  infos: n_rounds entries or NULL. */
 int abcsmc_run(const abcsmc_config* cfg, const int64_t* obs, int32_t n_rounds, double* theta,

@@ -359,6 +359,8 @@ typedef struct {
     double mcmc_s0;                    /* schedule 2: initial step size s */
     int32_t mcmc_tune;                 /* schedule 2: batches of stages >= 1 after which s is adapted */
     double beta_b_real;                /* schedules 3, 4: the stage's real Beta shape b (set by ref_run) */
+    int32_t n_eps_schedule;            /* stages 1..n accept against eps_schedule[i-1] instead of */
+    const double* eps_schedule;        /* eq. 8's percentile of stage i-1 (a replayed schedule) */
 } ref_config;
 
 enum { REF_S = 0, REF_I, REF_A, REF_R, REF_D, REF_RU };
@@ -777,7 +779,7 @@ int ref_run(const ref_config* cfg, const int64_t* obs, int32_t n_rounds, ref_res
         } else {
             const double* u_prev = out->u + (size_t)(r - 1) * N * REF_NPAR;
             const double* d_prev = out->dist + (size_t)(r - 1) * N;
-            double eps = out->eps_next[r - 1];
+            double eps = r <= cfg->n_eps_schedule ? cfg->eps_schedule[r - 1] : out->eps_next[r - 1];
             out->eps[r] = eps;
             if (r == 1) eps1 = eps;
             double ba; int32_t bb;

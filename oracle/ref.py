@@ -40,7 +40,7 @@ class Config(C.Structure):
         ("beta_b", C.c_int32), ("step_is_variance", C.c_int32), ("sampler", C.c_int32),
         ("max_attempts", C.c_int32), ("seed", C.c_uint64), ("max_proposals", C.c_int64),
         ("batch", C.c_int64), ("mcmc_s0", C.c_double), ("mcmc_tune", C.c_int32),
-        ("beta_b_real", C.c_double),
+        ("beta_b_real", C.c_double), ("n_eps_schedule", C.c_int32), ("eps_schedule", C.c_void_p),
     ]
 
 
@@ -125,6 +125,10 @@ def make_config(w, **over) -> Config:
     c.batch = w.batch
     c.mcmc_s0 = w.mcmc_s0
     c.mcmc_tune = w.mcmc_tune
+    sched = np.ascontiguousarray(getattr(w, "eps_schedule", ()), dtype=np.float64)
+    c._eps_keep = sched                     # alive as long as the config
+    c.n_eps_schedule = len(sched)
+    c.eps_schedule = sched.ctypes.data if len(sched) else None
     return c
 
 

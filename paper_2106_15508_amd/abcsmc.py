@@ -20,15 +20,17 @@ from . import workloads as W
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libabcsmc_hip.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 OK, EINVAL, ENOMEM, EDEVICE, EBUDGET, ESTATE, EDEGENERATE = 0, -1, -2, -3, -4, -5, -6
 F_EARLY_EXIT = 1
 F_STEP_IS_VARIANCE = 2
+F_SKIP_WEIGHTS = 4
 
 #: every function the header declares
 EXPORTS = (
     "abcsmc_workspace_size", "abcsmc_init", "abcsmc_round", "abcsmc_weights", "abcsmc_population",
-    "abcsmc_resampling", "abcsmc_reset", "abcsmc_rounds_done", "abcsmc_run", "abcsmc_simulate", "abcsmc_debug_eval",
+    "abcsmc_resampling", "abcsmc_reset", "abcsmc_rounds_done", "abcsmc_snapshot", "abcsmc_restore",
+    "abcsmc_run", "abcsmc_simulate", "abcsmc_debug_eval",
     "abcsmc_free", "abcsmc_strerror", "abcsmc_last_error", "abcsmc_abi_version",
     "abcsmc_batch_workspace_size", "abcsmc_batch_init", "abcsmc_batch_set_schedule",
     "abcsmc_batch_get_schedule", "abcsmc_batch_autotune", "abcsmc_batch_round", "abcsmc_batch_run",
@@ -56,6 +58,7 @@ class Config(C.Structure):
         ("flags", C.c_int32), ("max_attempts", C.c_int32), ("seed", C.c_uint64),
         ("max_proposals", C.c_int64), ("stream", C.c_void_p), ("workspace", C.c_void_p),
         ("workspace_bytes", C.c_size_t), ("mcmc_s0", C.c_double), ("mcmc_tune", C.c_int32),
+        ("n_eps_schedule", C.c_int32), ("eps_schedule", C.c_void_p),
     ]
 
 
@@ -165,6 +168,8 @@ def load(path: Optional[str] = None):
         "abcsmc_mlp_gradients": (C.c_int, [vp, i64, vp, vp, vp, vp]),
         "abcsmc_mlp_train": (C.c_int, [vp, i64, vp, vp, i32, i32, d, vp]),
         "abcsmc_predict": (C.c_int, [vp, i32, u64, i32, vp, vp]),
+        "abcsmc_snapshot": (C.c_int, [vp, vp, vp]),
+        "abcsmc_restore": (C.c_int, [vp, vp, vp, C.c_size_t, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -210,6 +215,10 @@ def make_config(w: W.Workload, *, stream=None, workspace=None, flags: int = 0, *
     c.max_proposals = w.max_proposals
     c.mcmc_s0 = w.mcmc_s0
     c.mcmc_tune = w.mcmc_tune
+    sched = np.ascontiguousarray(w.eps_schedule, dtype=np.float64)
+    c._eps_keep = sched                     # the library copies it at init
+    c.n_eps_schedule = len(sched)
+    c.eps_schedule = sched.ctypes.data if len(sched) else None
     c.stream = stream
     if workspace is not None:
         ptr, nbytes = workspace
@@ -251,14 +260,29 @@ def debug_eval(fn: int, inp: np.ndarray, n: int, out: np.ndarray, pa: float = 0.
 class Context:
     """One ABC-SMC run on the GPU (abcsmc_init ... abcsmc_free)."""
 
-    def __init__(self, w: W.Workload, obs, *, stream=None, workspace=None, flags: int = 0, **over):
+    def __init__(self, w: W.Workload, obs, *, stream=None, workspace=None, flags: int = 0,
+                 snapshot: Optional[bytes] = None, **over):
         self.w = w.with_(**over) if over else w
         self.cfg = make_config(self.w, stream=stream, workspace=workspace, flags=flags)
         self.obs = np.ascontiguousarray(obs, dtype=np.int64)
         self._h = C.c_void_p()
         self.L = load()
-        _check(self.L.abcsmc_init(C.byref(self.cfg), _p(self.obs), C.byref(self._h)))
+        if snapshot is None:
+            _check(self.L.abcsmc_init(C.byref(self.cfg), _p(self.obs), C.byref(self._h)))
+        else:
+            buf = C.create_string_buffer(bytes(snapshot), len(snapshot))
+            _check(self.L.abcsmc_restore(C.byref(self.cfg), _p(self.obs), buf, len(snapshot), C.byref(self._h)))
         self.infos: List[dict] = []
+
+    def snapshot(self) -> bytes:
+        """Checkpoint after the last completed stage (abcsmc_snapshot); pass it
+        as Context(..., snapshot=...) with the same workload and observations
+        to continue the run."""
+        n = C.c_size_t(0)
+        _check(self.L.abcsmc_snapshot(self._h, None, C.byref(n)), self._h)
+        buf = C.create_string_buffer(n.value)
+        _check(self.L.abcsmc_snapshot(self._h, buf, C.byref(n)), self._h)
+        return buf.raw[: n.value]
 
     @property
     def N(self) -> int:

@@ -124,6 +124,8 @@ int bvalidate(const abcsmc_config& c, const int64_t* obs, std::string* e)
     size_t dummy;
     if (c.step_schedule != ABCSMC_STEP_PAPER && c.step_schedule != ABCSMC_STEP_FIXED)
         return bfail(e, ABCSMC_EINVAL, "batched runs: eq. 16 or fixed Beta step schedules only");
+    if (c.n_eps_schedule != 0) return bfail(e, ABCSMC_EINVAL, "batched runs: no tolerance schedule");
+    if (c.flags & ABCSMC_F_SKIP_WEIGHTS) return bfail(e, ABCSMC_EINVAL, "batched runs: weights are always computed");
     abcsmc_config cc = c;
     cc.batch = 0;
     const int rc = abcsmc_workspace_size(&cc, &dummy);

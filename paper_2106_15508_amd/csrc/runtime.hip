@@ -112,7 +112,16 @@ int validate(const abcsmc_config* c, const int64_t* obs, std::string* err)
         return fail(err, ABCSMC_EINVAL, "fixed Beta needs a > 0 and integer 1 <= b <= 64");
     if (c->sampler != ABCSMC_SAMPLER_BINOMIAL && c->sampler != ABCSMC_SAMPLER_NORMAL_FLOOR)
         return fail(err, ABCSMC_EINVAL, "unknown sampler");
-    if (c->flags & ~(ABCSMC_F_EARLY_EXIT | ABCSMC_F_STEP_IS_VARIANCE)) return fail(err, ABCSMC_EINVAL, "unknown flags");
+    if (c->flags & ~(ABCSMC_F_EARLY_EXIT | ABCSMC_F_STEP_IS_VARIANCE | ABCSMC_F_SKIP_WEIGHTS))
+        return fail(err, ABCSMC_EINVAL, "unknown flags");
+    if (c->n_eps_schedule < 0 || c->n_eps_schedule > 4096)
+        return fail(err, ABCSMC_EINVAL, "n_eps_schedule must be in [0, 4096]");
+    if (c->n_eps_schedule > 0) {
+        if (!c->eps_schedule) return fail(err, ABCSMC_EINVAL, "eps_schedule is NULL");
+        for (int32_t i = 0; i < c->n_eps_schedule; ++i)
+            if (!(c->eps_schedule[i] >= 0.0) || !std::isfinite(c->eps_schedule[i]))
+                return fail(err, ABCSMC_EINVAL, "eps_schedule values must be finite and >= 0");
+    }
     if (c->max_attempts < 0 || c->max_attempts > 4096) return fail(err, ABCSMC_EINVAL, "max_attempts must be in [0, 4096]");
     if (c->max_proposals < 0) return fail(err, ABCSMC_EINVAL, "max_proposals must be >= 0");
     if (obs) {
@@ -224,6 +233,8 @@ int abcsmc_init(const abcsmc_config* cfg, const int64_t* obs, abcsmc_ctx** out)
     if (x->cfg.max_proposals == 0 || x->cfg.max_proposals > cap)
         x->cfg.max_proposals = std::min<int64_t>(cap, x->cfg.max_proposals ? x->cfg.max_proposals : 4096 * x->N);
     x->obs.assign(obs, obs + (size_t)(cfg->n_days + 1) * 3);
+    x->eps_sched.assign(cfg->eps_schedule, cfg->eps_schedule + cfg->n_eps_schedule);
+    x->cfg.eps_schedule = x->eps_sched.empty() ? nullptr : x->eps_sched.data();
     x->mcmc_s = cfg->mcmc_s0;
     x->model = make_model(x->cfg, obs);
     x->L = make_layout(x->cfg);
@@ -310,7 +321,8 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
     double* scal = x->at<double>(x->L.scal);
     hipStream_t s = x->stream;
 
-    const double eps = r == 0 ? INFINITY : x->eps_next;
+    // eq. 8's percentile of the last stage, or the replayed schedule
+    const double eps = r == 0 ? INFINITY : (r <= c.n_eps_schedule ? x->eps_sched[(size_t)r - 1] : x->eps_next);
     double ba = 0.0, bb_real = 0.0;
     int32_t bb = 0;
     const bool general = c.step_schedule == ABCSMC_STEP_MEANVAR || c.step_schedule == ABCSMC_STEP_MODECONC;
@@ -453,7 +465,8 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
     }
     if (r > 0) x->last_rate = (double)N / (double)hc.proposals;
     HIPCHK(x, hipEventRecord(x->ev[2], s));
-    if (r == 0) {
+    const bool weighted = r > 0 && !(c.flags & ABCSMC_F_SKIP_WEIGHTS);
+    if (!weighted) {
         launch_uniform_weights(dst.W, dst.logw, N, s);
     } else {
         WeightArgs wa{};
@@ -522,7 +535,7 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
         I.eps_next = hs[0];
         I.beta_a = ba;
         I.beta_b = bb;
-        I.ess = r == 0 ? (double)N : hs[1];
+        I.ess = weighted ? hs[1] : (double)N;
         I.proposals = (int64_t)hc.proposals;
         I.simulated = base;
         I.invalid = (int64_t)hc.invalid;
@@ -535,10 +548,10 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
         I.ms_select = elapsed(x->ev[3], x->ev[4]);
         I.ms_total = elapsed(x->ev[0], x->ev[4]);
         I.ms_k_propose = ms_k_propose;
-        I.ms_k_weights = r == 0 ? 0.0 : elapsed(x->ev[7], x->ev[8]);
+        I.ms_k_weights = weighted ? elapsed(x->ev[7], x->ev[8]) : 0.0;
         I.n_k_propose = batches;
         I.sim_days = (int64_t)hc.days;
-        I.weight_pairs = r == 0 ? 0 : (int64_t)N * (int64_t)hc.survivors;
+        I.weight_pairs = weighted ? (int64_t)N * (int64_t)hc.survivors : 0;
         I.weight_terms = (int64_t)hterms;
         I.mcmc_s = mcmc ? x->mcmc_s : 0.0;
         I.beta_b_real = general ? bb_real : (double)bb;

@@ -71,6 +71,7 @@ class Workload:
     theta_true: Sequence[float] = THETA_TRUE
     mcmc_s0: float = 0.1      # STEP_MCMC: initial step size
     mcmc_tune: int = 100      # STEP_MCMC: tuned batches (the first 10% of a 1000-run budget)
+    eps_schedule: Sequence[float] = ()  # tolerances replayed in stages 1.. (eq. 8 afterwards)
 
     @property
     def a0(self) -> int:

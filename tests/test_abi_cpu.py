@@ -60,6 +60,30 @@ def test_invalid_prior_and_fixed_beta_rejected():
     assert A.load().abcsmc_workspace_size(C.byref(c), C.byref(n)) == A.EINVAL
 
 
+@pytest.mark.parametrize("sched", [(1.0, float("nan")), (-1.0,), (float("inf"),)])
+def test_invalid_eps_schedule_rejected(sched):
+    c = A.make_config(W.C1, eps_schedule=sched)
+    n = C.c_size_t()
+    assert A.load().abcsmc_workspace_size(C.byref(c), C.byref(n)) == A.EINVAL
+    c = A.make_config(W.C1)
+    c.n_eps_schedule = 2  # no array
+    assert A.load().abcsmc_workspace_size(C.byref(c), C.byref(n)) == A.EINVAL
+    c.n_eps_schedule = 5000
+    assert A.load().abcsmc_workspace_size(C.byref(c), C.byref(n)) == A.EINVAL
+
+
+def test_restore_rejects_malformed_snapshots():
+    # checked before any device work
+    L = A.load()
+    c = A.make_config(W.C1)
+    obs = np.zeros((W.C1.n_days + 1, 3), np.int64)
+    h = C.c_void_p()
+    for buf in (b"", b"x" * 16, b"ABCSMCK1" + b"\0" * 200):
+        b = C.create_string_buffer(buf, max(len(buf), 1))
+        assert L.abcsmc_restore(C.byref(c), obs.ctypes.data_as(C.c_void_p), b, len(buf), C.byref(h)) == A.EINVAL
+        assert not h.value
+
+
 def test_init_rejects_bad_observations():
     L = A.load()
     c = A.make_config(W.C1)

@@ -199,3 +199,17 @@ def test_bdss_beats_fixed_step(oracle):
     paper = oracle.run(w.with_(step_schedule=W.STEP_PAPER), obs)
     fixed = oracle.run(w.with_(step_schedule=W.STEP_FIXED), obs)
     assert paper.eps_next[-1] < fixed.eps_next[-1]
+
+
+def test_replaying_own_schedule_is_identity(oracle):
+    # a run fed its own eq. 8 tolerances is the same run; a changed entry
+    # changes exactly the stage that uses it (and what follows from it)
+    wl = W.tiny(n_rounds=4)
+    obs = oracle.observations(wl)
+    a = oracle.run(wl, obs)
+    b = oracle.run(wl.with_(eps_schedule=tuple(a.eps_next[:3])), obs)
+    assert np.array_equal(a.u, b.u) and np.array_equal(a.dist, b.dist)
+    assert np.array_equal(a.eps, b.eps) and np.array_equal(a.W, b.W)
+    c = oracle.run(wl.with_(eps_schedule=(a.eps_next[0], 0.8 * a.eps_next[1])), obs)
+    assert np.array_equal(a.u[:2], c.u[:2]) and c.eps[2] == 0.8 * a.eps_next[1]
+    assert np.all(c.dist[2] <= c.eps[2]) and not np.array_equal(a.u[2], c.u[2])

@@ -235,6 +235,18 @@ void ref_box_muller(uint64_t w, double* z0, double* z1)
 #define REF_T_SWITCH 10.0
 #define REF_BINV_CAP 128
 
+/* 1/j for j = 1..REF_BINV_CAP, each the correctly rounded double */
+static double binv_recip(int64_t j)
+{
+    static double tab[REF_BINV_CAP + 1];
+    static int ready = 0;
+    if (!ready) {
+        for (int i = 1; i <= REF_BINV_CAP; ++i) tab[i] = 1.0 / (double)i;
+        ready = 1;
+    }
+    return tab[j];
+}
+
 int64_t ref_binomial(int64_t n, double p, uint64_t w)
 {
     if (n <= 0 || p <= 0.0) return 0;
@@ -245,14 +257,16 @@ int64_t ref_binomial(int64_t n, double p, uint64_t w)
     double m = dn * q;
     int64_t x;
     if (m < REF_T_SWITCH) {
-        /* inversion by sequential search (BINV): F(k) accumulates the pmf */
+        /* inversion by sequential search (BINV): F(k) accumulates the pmf,
+         * f(k+1) = f(k) (n - k) r / (k + 1) with the division taken as a
+         * product with the rounded reciprocal 1/(k+1) */
         double u = ref_u01(w);
         double f = ref_exp(dn * ref_log1p(-q));
         double F = f;
         double r = q / (1.0 - q);
         int64_t k = 0;
         while (u > F && k < n && k < REF_BINV_CAP) {
-            f = f * (((double)(n - k) * r) / (double)(k + 1));
+            f = f * (((double)(n - k) * r) * binv_recip(k + 1));
             k = k + 1;
             F = F + f;
         }

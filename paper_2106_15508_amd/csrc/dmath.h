@@ -333,6 +333,18 @@ __device__ __forceinline__ double beta_general(double a, double b, uint64_t seed
 constexpr double kTSwitch = 10.0;
 constexpr int kBinvCap = 128;
 
+// 1/j, j = 1..kBinvCap, rounded to nearest at compile time.  The inversion
+// loop's step counter is the same in every lane still searching, so the
+// entry is a wave-uniform (scalar) load.
+struct RecipTab {
+    double v[kBinvCap + 1];
+    constexpr RecipTab() : v{}
+    {
+        for (int j = 1; j <= kBinvCap; ++j) v[j] = 1.0 / (double)j;
+    }
+};
+__device__ constexpr RecipTab kRecip{};
+
 // Bin(n, p) from one word; n is an exact integer held in a double.
 __device__ __forceinline__ double binomial(double n, double p, uint64_t w)
 {
@@ -348,8 +360,8 @@ __device__ __forceinline__ double binomial(double n, double p, uint64_t w)
         double F = f;
         const double r = q / (1.0 - q);
         double k = 0.0;
-        while (u > F && k < n && k < (double)kBinvCap) {
-            f = f * (((n - k) * r) / (k + 1.0));
+        for (int it = 0; it < kBinvCap && u > F && k < n; ++it) {
+            f = f * (((n - k) * r) * kRecip.v[it + 1]);  // (n - k) r / (k + 1), k = it
             k = k + 1.0;
             F = F + f;
         }

@@ -143,7 +143,7 @@ int abcsmc_restore(const abcsmc_config* cfg, const int64_t* obs, const void* buf
     std::memcpy(&h, buf, sizeof h);
     if (std::memcmp(h.magic, kMagic, sizeof kMagic) != 0 || h.abi != ABCSMC_ABI_VERSION)
         return fail(nullptr, ABCSMC_EINVAL, "not a snapshot of this library version");
-    if (h.rounds < 1 || h.N < 2 || bytes != snapshot_bytes(h.N))
+    if (h.rounds < 1 || h.N < 2 || h.N > ((int64_t)1 << 22) || bytes != snapshot_bytes(h.N))
         return fail(nullptr, ABCSMC_EINVAL, "malformed snapshot");
     abcsmc_ctx* x = nullptr;
     int rc = abcsmc_init(cfg, obs, &x);

@@ -83,6 +83,18 @@ def test_snapshot_needs_a_completed_stage(oracle):
         assert e.value.code == A.ESTATE
 
 
+def test_snapshot_refused_with_the_learned_screen(oracle):
+    wl = W.tiny(n_rounds=2)
+    with A.Context(wl, oracle.observations(wl)) as ctx:
+        ctx.round()
+        ctx.surrogate_enable(n_train=4096, epochs=1, batch=256, seed=1)
+        with pytest.raises(A.AbcsmcError) as e:
+            ctx.snapshot()
+        assert e.value.code == A.ESTATE
+        ctx.surrogate_disable()
+        assert len(ctx.snapshot()) > 0
+
+
 def test_replayed_schedule_matches_oracle(oracle):
     wl = W.tiny(n_rounds=4)
     obs = oracle.observations(wl)

@@ -461,10 +461,11 @@ class Batch:
         self.ws = list(workloads)
         self.R = len(self.ws)
         cfgs = (Config * self.R)()
-        for r, w in enumerate(self.ws):
-            cfgs[r] = make_config(w, stream=stream if r == 0 else None,
-                                  workspace=workspace if r == 0 else None, flags=flags)
-        self._cfgs = cfgs
+        made = [make_config(w, stream=stream if r == 0 else None, workspace=workspace if r == 0 else None,
+                            flags=flags) for r, w in enumerate(self.ws)]
+        for r, c in enumerate(made):
+            cfgs[r] = c
+        self._cfgs, self._made = cfgs, made  # keep any schedule arrays alive
         self._obs = [np.ascontiguousarray(o, dtype=np.int64) for o in obs_list]
         ptrs = (C.c_void_p * self.R)(*[o.ctypes.data for o in self._obs])
         self._h = C.c_void_p()
@@ -475,8 +476,9 @@ class Batch:
     def workspace_size(workloads, flags: int = 0) -> int:
         R = len(workloads)
         cfgs = (Config * R)()
-        for r, w in enumerate(workloads):
-            cfgs[r] = make_config(w, flags=flags)
+        made = [make_config(w, flags=flags) for w in workloads]  # alive for the call
+        for r, c in enumerate(made):
+            cfgs[r] = c
         n = C.c_size_t()
         _bcheck(load().abcsmc_batch_workspace_size(cfgs, R, C.byref(n)))
         return n.value

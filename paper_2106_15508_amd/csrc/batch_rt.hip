@@ -118,14 +118,21 @@ WinLayout win_layout(size_t o, size_t n_total, size_t n_fin)
     return L;
 }
 
-// validation shared with the single-run path's rules (subset relevant here)
-int bvalidate(const abcsmc_config& c, const int64_t* obs, std::string* e)
+// what batched runs do not support, on top of the single-run rules
+int bunsupported(const abcsmc_config& c, std::string* e)
 {
-    size_t dummy;
     if (c.step_schedule != ABCSMC_STEP_PAPER && c.step_schedule != ABCSMC_STEP_FIXED)
         return bfail(e, ABCSMC_EINVAL, "batched runs: eq. 16 or fixed Beta step schedules only");
     if (c.n_eps_schedule != 0) return bfail(e, ABCSMC_EINVAL, "batched runs: no tolerance schedule");
     if (c.flags & ABCSMC_F_SKIP_WEIGHTS) return bfail(e, ABCSMC_EINVAL, "batched runs: weights are always computed");
+    return ABCSMC_OK;
+}
+
+// validation shared with the single-run path's rules (subset relevant here)
+int bvalidate(const abcsmc_config& c, const int64_t* obs, std::string* e)
+{
+    size_t dummy;
+    if (const int u = bunsupported(c, e)) return u;
     abcsmc_config cc = c;
     cc.batch = 0;
     const int rc = abcsmc_workspace_size(&cc, &dummy);
@@ -322,6 +329,7 @@ int abcsmc_batch_workspace_size(const abcsmc_config* cfgs, int32_t n_runs, size_
         cc.batch = 0;
         const int rc = abcsmc_workspace_size(&cc, &dummy);
         if (rc) return rc;
+        if (const int u = bunsupported(cfgs[r], nullptr)) return u;
         const RunLayout L = run_layout(cfgs[r], o);
         o = L.end;
         n_res += (int)((cfgs[r].n_particles + 1023) / 1024);

@@ -72,6 +72,15 @@ def test_invalid_eps_schedule_rejected(sched):
     assert A.load().abcsmc_workspace_size(C.byref(c), C.byref(n)) == A.EINVAL
 
 
+@pytest.mark.parametrize("over,flags", [(dict(eps_schedule=(5.0,)), 0), ({}, A.F_SKIP_WEIGHTS),
+                                        (dict(step_schedule=W.STEP_MEANVAR), 0)])
+def test_batch_rejects_unsupported_options(over, flags):
+    runs = [W.tiny(seed=3), W.tiny(seed=4, **over)]
+    with pytest.raises(A.AbcsmcError) as e:
+        A.Batch.workspace_size(runs, flags=flags)
+    assert e.value.code == A.EINVAL
+
+
 def test_restore_rejects_malformed_snapshots():
     # checked before any device work
     L = A.load()

@@ -154,3 +154,25 @@ def test_uneven_batch_sampled_runs_match_plain(oracle):
             assert np.array_equal(_bits(p["u"]), _bits(plain[2]["u"]))
             assert np.array_equal(_bits(p["d"]), _bits(plain[2]["d"]))
             np.testing.assert_allclose(p["W"], plain[2]["W"], rtol=1e-12, atol=0)
+
+
+def test_full_c4_batch_sampled(oracle):
+    """The benchmark's batch (96 uneven runs, 10 stages, early exit): sampled
+    runs equal the same runs alone, and sampled particles of the last stage
+    re-simulate to the same distances in the oracle."""
+    runs = W.batched_runs()
+    obs = [oracle.observations(w) for w in runs]
+    R = runs[0].n_rounds
+    with A.Batch(runs, obs, flags=A.F_EARLY_EXIT) as b:
+        infos = b.run(R)
+        sizes = [w.n_particles * w.n_days for w in runs]
+        picks = (int(np.argmin(sizes)), int(np.argmax(sizes)), 37)
+        pops = {r: b.population(r) for r in picks}
+    for r in picks:
+        plain = _plain(runs[r], obs[r], R, A.F_EARLY_EXIT)
+        _same(pops[r], plain[-1], infos[-1][r], plain[-1]["info"])
+        p = pops[r]
+        eps = infos[-1][r]["eps"]
+        for j in np.random.default_rng(r).choice(runs[r].n_particles, 4, replace=False):
+            d = oracle.sim_distance(runs[r], obs[r], p["u"][j], R - 1, int(p["index"][j]))
+            assert d == p["d"][j] and d <= eps, (r, j)

@@ -4,7 +4,9 @@ workspace and stream, early exit on, library-chosen batches).
 C2 (P=1e7, T=120, N=131072): stages 0 and 1 are recomputed completely by the
 oracle (process pool) and compared bit for bit, including eps^1 and eps^2;
 importance weights on sampled rows within 1e-12.  C3 (P=3e8, T=180,
-N=2^20): sampled stage-0 particles bit for bit, invariants of stage 1."""
+N=2^20): sampled stage-0 particles bit for bit, invariants of stage 1.  C5
+(C2 with the learned screen at the benchmark's settings): sampled
+acceptances of the first screened stage against the oracle."""
 import numpy as np
 import pytest
 
@@ -108,3 +110,47 @@ def test_c3_sampled_and_invariants(oracle):
     assert q.max() == 2**40 and q[np.argmin(d0)] == 2**40
     assert np.array_equal(cdf, np.cumsum(q.astype(object)).astype(np.uint64))
     assert st["info"]["survivors"] == int(np.count_nonzero(q))
+
+
+def test_c5_screened_stage_sampled(oracle):
+    """The learned screen at the benchmark's configuration (fit on 2^22
+    prior simulations, keep 10%, audit 1%): sampled acceptances of the first
+    screened stage are the oracle's own perturbations and simulations, within
+    eps, with the oracle's log-weight (minus log rho when kept by the audit);
+    no acceptable proposal that the audit kept is missing."""
+    import math
+
+    from oracle import mlp_ref as M
+    w = W.C2
+    obs = A.observations(w)
+    sur = dict(n_train=1 << 22, epochs=2, batch=8192, keep_frac=0.1, audit_rho=0.01, fn_max=1.0, seed=11)
+    with A.Context(w, obs, flags=A.F_EARLY_EXIT) as ctx:
+        ctx.round()
+        p0 = ctx.population()
+        _, d0, _ = ctx.weights()
+        ctx.surrogate_enable(**sur)
+        info = ctx.round()
+        pop = ctx.population()
+        _, d1, _ = ctx.weights()
+        audit = ctx.surrogate_audit()
+    eps = info["eps"]
+    q, Cc, _ = oracle.resample_weights(d0, eps)
+    idx = pop["index"]
+    rng = np.random.default_rng(5)
+    for k in rng.choice(w.n_particles, 24, replace=False):
+        j = int(idx[k])
+        a, u, s, par = oracle.perturb(w, 1, j, p0["u"], Cc, 1.0, 2)
+        assert a > 0 and np.array_equal(pop["u"][k], u) and pop["sigma"][k] == s and pop["parent"][k] == par, j
+        dj = oracle.sim_distance(w, obs, u, 1, j)
+        assert dj == d1[k] and dj <= eps, j
+        if audit[k]:
+            assert M.audit_u(w.seed, 1, j) < sur["audit_rho"], j
+        lo = oracle.log_weight(u, s, p0["u"], q) - (math.log(sur["audit_rho"]) if audit[k] else 0.0)
+        assert abs(pop["logw"][k] - lo) <= 1e-12 * max(1.0, abs(lo)), j
+    accepted = set(idx.tolist())
+    for j in rng.choice(int(idx[-1]) + 1, 300, replace=False):
+        j = int(j)
+        if j in accepted or M.audit_u(w.seed, 1, j) >= sur["audit_rho"]:
+            continue
+        a, u, _, _ = oracle.perturb(w, 1, j, p0["u"], Cc, 1.0, 2)
+        assert a < 0 or oracle.sim_distance(w, obs, u, 1, j) > eps, j

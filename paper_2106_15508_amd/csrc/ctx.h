@@ -100,6 +100,8 @@ struct abcsmc_ctx {
     double eps_next = INFINITY;  // eps of the next stage
     double eps1 = INFINITY;      // eps of stage 1 (eq. 16 normaliser)
     std::vector<double> eps_sched;  // replayed tolerances of stages 1.. (cfg.eps_schedule points here)
+    char* stage_host = nullptr;  // pinned staging for the copy-out calls (allocated on first use)
+    size_t stage_bytes = 0;
     double last_rate = 0.5;      // acceptance rate of the last stage (batch sizing)
     double mcmc_s = 0.0;         // MCMC variant: current step size
     int32_t mcmc_tunes = 0;      // MCMC variant: tuned batches so far

@@ -212,6 +212,7 @@ void abcsmc_free(abcsmc_ctx* ctx)
     surrogate_free(ctx->sur);
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    if (ctx->stage_host) (void)hipHostFree(ctx->stage_host);
     if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -563,6 +564,51 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
 
 extern "C" {
 
+namespace {
+
+// Device-to-host copies of up to kCopies arrays through the context's pinned
+// staging buffer (pinned transfers run at link speed; pageable ones are
+// staged by the runtime in small pieces), then one host copy per array.
+struct CopyOut {
+    void* dst;
+    const void* src;
+    size_t bytes;
+};
+
+int copy_out(abcsmc_ctx* x, const CopyOut* c, int n)
+{
+    size_t total = 0;
+    for (int k = 0; k < n; ++k)
+        if (c[k].dst) total += (c[k].bytes + 255) / 256 * 256;
+    if (total > x->stage_bytes) {
+        if (x->stage_host) (void)hipHostFree(x->stage_host);
+        x->stage_host = nullptr;
+        x->stage_bytes = 0;
+        if (hipHostMalloc((void**)&x->stage_host, total, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            x->stage_host = nullptr;
+            return fail(&x->err, ABCSMC_ENOMEM, "hipHostMalloc of the copy-out staging failed");
+        }
+        x->stage_bytes = total;
+    }
+    size_t off = 0;
+    for (int k = 0; k < n; ++k) {
+        if (!c[k].dst) continue;
+        HIPCHK(x, hipMemcpyAsync(x->stage_host + off, c[k].src, c[k].bytes, hipMemcpyDeviceToHost, x->stream));
+        off += (c[k].bytes + 255) / 256 * 256;
+    }
+    HIPCHK(x, hipStreamSynchronize(x->stream));
+    off = 0;
+    for (int k = 0; k < n; ++k) {
+        if (!c[k].dst) continue;
+        std::memcpy(c[k].dst, x->stage_host + off, c[k].bytes);
+        off += (c[k].bytes + 255) / 256 * 256;
+    }
+    return ABCSMC_OK;
+}
+
+}  // namespace
+
 int abcsmc_weights(const abcsmc_ctx* cx, double* theta, double* dist, double* weight)
 {
     abcsmc_ctx* x = const_cast<abcsmc_ctx*>(cx);
@@ -572,16 +618,15 @@ int abcsmc_weights(const abcsmc_ctx* cx, double* theta, double* dist, double* we
     const DevPop& p = x->pop[x->cur];
     const size_t N = (size_t)x->N;
     hipStream_t s = x->stream;
+    double* th = x->at<double>(x->L.theta);
     if (theta) {
-        double* th = x->at<double>(x->L.theta);
         launch_to_theta(p.u, x->model, th, (int64_t)N, s);
         HIPCHK(x, hipGetLastError());
-        HIPCHK(x, hipMemcpyAsync(theta, th, N * kNP * sizeof(double), hipMemcpyDeviceToHost, s));
     }
-    if (dist) HIPCHK(x, hipMemcpyAsync(dist, p.d, N * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (weight) HIPCHK(x, hipMemcpyAsync(weight, p.W, N * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(x, hipStreamSynchronize(s));
-    return ABCSMC_OK;
+    const CopyOut c[3] = {{theta, th, N * kNP * sizeof(double)},
+                          {dist, p.d, N * sizeof(double)},
+                          {weight, p.W, N * sizeof(double)}};
+    return copy_out(x, c, 3);
 }
 
 int abcsmc_population(const abcsmc_ctx* cx, double* u, double* sigma, int64_t* parent, int64_t* index,
@@ -593,16 +638,15 @@ int abcsmc_population(const abcsmc_ctx* cx, double* u, double* sigma, int64_t* p
     if (x->rounds == 0) return fail(&x->err, ABCSMC_ESTATE, "no completed stage");
     const DevPop& p = x->pop[x->cur];
     const size_t N = (size_t)x->N;
-    hipStream_t s = x->stream;
     std::vector<int32_t> pi(parent ? N : 0);
     std::vector<uint32_t> ii(index ? N : 0);
-    if (u) HIPCHK(x, hipMemcpyAsync(u, p.u, N * kNP * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (sigma) HIPCHK(x, hipMemcpyAsync(sigma, p.sigma, N * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (parent) HIPCHK(x, hipMemcpyAsync(pi.data(), p.parent, N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    if (index) HIPCHK(x, hipMemcpyAsync(ii.data(), p.index, N * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    if (attempts) HIPCHK(x, hipMemcpyAsync(attempts, p.att, N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    if (logw) HIPCHK(x, hipMemcpyAsync(logw, p.logw, N * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(x, hipStreamSynchronize(s));
+    const CopyOut c[6] = {{u, p.u, N * kNP * sizeof(double)},
+                          {sigma, p.sigma, N * sizeof(double)},
+                          {parent ? pi.data() : nullptr, p.parent, N * sizeof(int32_t)},
+                          {index ? ii.data() : nullptr, p.index, N * sizeof(uint32_t)},
+                          {attempts, p.att, N * sizeof(int32_t)},
+                          {logw, p.logw, N * sizeof(double)}};
+    if (const int rc = copy_out(x, c, 6)) return rc;
     for (size_t k = 0; k < pi.size(); ++k) parent[k] = pi[k];
     for (size_t k = 0; k < ii.size(); ++k) index[k] = ii[k];
     return ABCSMC_OK;

@@ -27,6 +27,10 @@ HIPCC_FLAGS = [
     "-fno-fast-math",
     # packed FP32 instructions are not emitted
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # FP64 fma as the three-operand v_fma_f64 only: with the two-operand
+    # v_fmac_f64 every Horner step whose addend is a loop-invariant
+    # coefficient held in a VGPR costs an extra v_mov_b64 (same results)
+    "-Xclang", "-target-feature", "-Xclang", "-fmacf64-inst",
     "-Wall",
     "-Wno-unused-command-line-argument",
 ]

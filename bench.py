@@ -44,10 +44,12 @@ FLOPS_PER_PAIR = 8 + 16 + 1 + 11 + 2
 # HBM bytes per launch of the dominant kernel measured with rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE on this workload, scaled by the counters' reading
 # for a 256 MiB device copy (FETCH 0.5x, WRITE 1.0x of the bytes moved).  Keyed
-# by the SHA-256 of the kernel sources: a changed kernel reports null.
+# by the SHA-256 of the kernel sources and the build flags: a changed kernel
+# reports null.
 TRAFFIC_SOURCES = ("paper_2106_15508_amd/csrc/smc.hip", "paper_2106_15508_amd/csrc/dmath.h",
                    "paper_2106_15508_amd/csrc/kernels.h", "paper_2106_15508_amd/csrc/wterm.h",
-                   "paper_2106_15508_amd/csrc/sim.hip", "paper_2106_15508_amd/csrc/propose.h")
+                   "paper_2106_15508_amd/csrc/sim.hip", "paper_2106_15508_amd/csrc/propose.h",
+                   "paper_2106_15508_amd/build.py")
 TRAFFIC_MEASURED = {
     # c2, per launch: FETCH_SIZE KiB x 2 + WRITE_SIZE KiB x 1
     ("6a420bd7f9020a47", "c2", "weights_kernel"): 223891 * 1024 * 2 + 33187 * 1024,

@@ -116,9 +116,9 @@ __device__ __forceinline__ double row_sum(const double* uj, double cj, const_col
     return total;
 }
 
-// Window of a row: a column whose sort coordinate differs by more than
-// kWindow sigma_j gives an exponent below -710, where both exponentials are
-// exactly 0, so it can be skipped without changing the sum.
+// Widest window of a row (the cap of window_halfwidth): a column whose sort
+// coordinate differs by more than kWindow sigma_j gives an exponent below
+// -710, where both exponentials are exactly 0.
 constexpr double kWindow = 37.7;
 
 // Narrower per-row window with a bound on what it leaves out.  Every column

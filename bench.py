@@ -195,8 +195,6 @@ def bench_batched(args):
                                f"N in {{2^11..2^16}} (sum N = {sum(w.n_particles for w in runs)}), {R} stages, "
                                "batched mode (one graph replay per stage)",
                    "early_exit": bool(args.early_exit), "schedule": sched, "autotune_s": round(tune_s, 2)},
-        "pcie_inclusive_value": accepted / (sec + sec_copy),
-        "ms_copy_out": round(sec_copy * 1e3, 3),
         "simulations_per_s": simulated / sec,
         "plain_sequential_value": accepted / sec_plain,
         "speedup_vs_plain": sec_plain / sec,

@@ -9,6 +9,7 @@ namespace abcsmc {
 constexpr int kNP = 8;        // parameters per particle (eq. 1)
 constexpr int kBlock = 256;   // threads per workgroup of the per-lane kernels
 constexpr int kWave = 64;
+constexpr int kWeightRows = 128;  // sorted rows per workgroup (and per window) of the weight kernel
 
 // Model constants shared by every simulation (§II-B).
 struct Model {

@@ -84,7 +84,7 @@ Layout make_layout(const abcsmc_config& c)
     L.skey = take(N * sizeof(double));
     L.dimpart = take(256 * 16 * sizeof(double));
     L.dstar = take(sizeof(int32_t));
-    L.win = take(((N + kBlock - 1) / kBlock) * sizeof(int2));
+    L.win = take(((N + kWeightRows - 1) / kWeightRows) * sizeof(int2));
     L.rwin = take(N * sizeof(double));
     L.total = o;
     return L;

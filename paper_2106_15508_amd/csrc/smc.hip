@@ -247,7 +247,7 @@ using wterm::wave_min;
 // where every omitted exponential is below e^-710).  Per stage: pick the
 // coordinate d* with the largest spread among the columns (the windows then
 // exclude the most columns: sigma is the same in every coordinate), sort the
-// columns by it, sort the rows by (octave of sigma, u_d*), and let every
+// columns by it, sort the rows by (octave of sigma, descending; u_d*), and let every
 // workgroup (128 consecutive sorted rows) visit only the union of its rows'
 // windows; a wave also skips tiles outside its own lanes' union.
 
@@ -329,7 +329,9 @@ __global__ __launch_bounds__(kBlock) void wrowkeys_kernel(WeightArgs a)
         return;
     }
     const int ds = *a.dstar;
-    const unsigned long long hi = (sigma_octave(a.sigma[i]) << 26) | (coord_key32(a.u[i * kNP + ds]) >> 6);
+    // octaves in descending order: the widest windows are dispatched first
+    const unsigned long long hi =
+        ((63ull - sigma_octave(a.sigma[i])) << 26) | (coord_key32(a.u[i * kNP + ds]) >> 6);
     a.rowkeys[i] = (hi << 32) | (unsigned long long)i;
     double uj[kNP];
 #pragma unroll

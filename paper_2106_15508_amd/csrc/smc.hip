@@ -379,7 +379,7 @@ __global__ __launch_bounds__(kWeightRows) void wwindow_kernel(WeightArgs a)
 // grid (row blocks, chunks): block (b, c) sums columns
 // [first_b + c CH, min(end_b, first_b + (c+1) CH)) for its kWeightRows rows
 // (two waves: 128-row blocks keep the windows tighter than 256-row ones, 3.5%
-// faster at N = 131072); chunks past the window write zero partials and leave.
+// faster at N = 131072); chunks past the window leave at once.
 __global__ __launch_bounds__(kWeightRows) void weights_kernel(WeightArgs a)
 {
     __shared__ double T[wterm::kTab];
@@ -388,10 +388,7 @@ __global__ __launch_bounds__(kWeightRows) void weights_kernel(WeightArgs a)
     const int2 wnd = a.win[blockIdx.x];
     const int k0 = wnd.x + (int)blockIdx.y * a.cols_per_chunk;
     const int k1 = min(wnd.y, k0 + a.cols_per_chunk);
-    if (k0 >= k1) {
-        if (active) a.partial[(size_t)blockIdx.y * a.N + r] = 0.0;
-        return;
-    }
+    if (k0 >= k1) return;  // past the window: the finalize pass does not read this chunk
     wterm::fill_table(T);
     __syncthreads();
     const int ds = *a.dstar;
@@ -425,8 +422,12 @@ __global__ __launch_bounds__(kBlock) void weights_finalize_kernel(WeightArgs a)
 {
     const int r = blockIdx.x * kBlock + threadIdx.x;
     if (r >= a.N) return;
+    // the chunks that overlap the row block's window, in order
+    const int2 wnd = a.win[r / kWeightRows];
+    const int len = wnd.y > wnd.x ? wnd.y - wnd.x : 0;
+    const int nch = min(a.chunks, (len + a.cols_per_chunk - 1) / a.cols_per_chunk);
     double L = 0.0;
-    for (int c = 0; c < a.chunks; ++c) L += a.partial[(size_t)c * a.N + r];
+    for (int c = 0; c < nch; ++c) L += a.partial[(size_t)c * a.N + r];
     const size_t j = (size_t)(a.rowkeys[r] & 0xFFFFFFFFull);
     a.logw[j] = 8.0 * dm::log(a.sigma[j]) - dm::log(L);
 }

@@ -53,7 +53,7 @@ struct BRun {
     int32_t res_blk0;          // first block of this run in the segmented resample grid
     int32_t res_nblk;
     int32_t off;               // first slot of this run in the batch-wide sort arrays (sum of earlier N)
-    int32_t rb0;               // first 256-row block of this run in the finalize / window tables
+    int32_t rb0;               // first 128-row block of this run in the finalize / window tables
 };
 
 // Mutable state of one run (device).
@@ -99,7 +99,7 @@ struct BatchArgs {
     double* scols;             // n_total x 9 sorted columns (u_k, q_k)
     double* skey;              // n_total sorted sort-coordinate values
     double* rwin;              // n_total per-row window half-widths (slot off_r + j)
-    int2* win;                 // per 256-row block: column window [x, y) within the run
+    int2* win;                 // per 128-row block: column window [x, y) within the run
     size_t npad;               // power-of-two sort length >= n_total
     int32_t n_total;           // sum of N_r
     int32_t n_key_blocks;      // ceil(npad / 256)

@@ -429,8 +429,8 @@ __global__ __launch_bounds__(kBlock) void bcompact_scatter_kernel(BatchArgs a)
 
 // Weight window, per run (as the single-run pass): the sort coordinate d* of
 // largest column variance; columns sorted by (run, u_{k,d*}); rows sorted by
-// (run, sigma octave, u_{j,d*}); each row's half-width comes from its parent's
-// term (wterm::window_halfwidth) and each 256-row block gets the union of its
+// (run, sigma octave descending, u_{j,d*}); each row's half-width comes from its parent's
+// term (wterm::window_halfwidth) and each 128-row block gets the union of its
 // rows' column ranges.  One batch-wide bitonic
 // sort per key set: the run index in the top 12 bits keeps every run's keys in
 // its own slot range [off_r, off_r + N_r).
@@ -505,7 +505,9 @@ __global__ __launch_bounds__(kBlock) void bkeys_kernel(BatchArgs a)
                        ? run | (coord_key32(R.cols[k * 9 + ds]) << 20) | k
                        : run | (0xFFFFFFFFull << 20) | k;
     const int nx = S.nxt;
-    a.rowkeys[i] = run | (sigma_octave(R.sigma[nx][k]) << 46) | ((coord_key32(R.u[nx][k * kNP + ds]) >> 6) << 20) | k;
+    // octaves in descending order: the widest windows are dispatched first
+    const unsigned long long oct = 63ull - sigma_octave(R.sigma[nx][k]);
+    a.rowkeys[i] = run | (oct << 46) | ((coord_key32(R.u[nx][k * kNP + ds]) >> 6) << 20) | k;
     const double* uj = R.u[nx] + k * kNP;
     const int32_t par = R.parent[nx][k];
     const bool ok = par >= 0 && par < R.N;
@@ -530,15 +532,15 @@ __global__ __launch_bounds__(kBlock) void bcolgather_kernel(BatchArgs a)
 }
 
 // One block per (run, 256 sorted rows): the block's column window.
-__global__ __launch_bounds__(kBlock) void bwindow_kernel(BatchArgs a)
+__global__ __launch_bounds__(kWeightRows) void bwindow_kernel(BatchArgs a)
 {
-    __shared__ double slo[kBlock / kWave], shi[kBlock / kWave];
+    __shared__ double slo[kWeightRows / kWave], shi[kWeightRows / kWave];
     const int2 fb = a.fin_tab[blockIdx.x];
     const BRun& R = a.runs[fb.x];
     const BState& S = a.st[fb.x];
     if (S.failed) return;
     const int nx = S.nxt;
-    const int rr = fb.y * kBlock + threadIdx.x;
+    const int rr = fb.y * kWeightRows + threadIdx.x;
     double lo = __builtin_inf(), hi = -__builtin_inf();
     if (rr < R.N) {
         const size_t j = (size_t)(a.rowkeys[R.off + rr] & 0xFFFFFull);
@@ -555,7 +557,7 @@ __global__ __launch_bounds__(kBlock) void bwindow_kernel(BatchArgs a)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int q = 0; q < kBlock / kWave; ++q) {
+        for (int q = 0; q < kWeightRows / kWave; ++q) {
             lo = slo[q] < lo ? slo[q] : lo;
             hi = shi[q] > hi ? shi[q] : hi;
         }
@@ -567,7 +569,7 @@ __global__ __launch_bounds__(kBlock) void bwindow_kernel(BatchArgs a)
 
 // grid = weight table (run, row block, chunk): chunk c of the block's window,
 // sorted rows; partial sums go to the rows' own indices (finalize unchanged).
-__global__ __launch_bounds__(kBlock) void bweights_kernel(BatchArgs a)
+__global__ __launch_bounds__(kWeightRows) void bweights_kernel(BatchArgs a)
 {
     __shared__ double T[wterm::kTab];
     const int4 wb = a.w_tab[blockIdx.x];
@@ -575,7 +577,7 @@ __global__ __launch_bounds__(kBlock) void bweights_kernel(BatchArgs a)
     const BState& S = a.st[wb.x];
     if (S.failed) return;  // uniform across the block
     const int nx = S.nxt;
-    const int rr = wb.y * kBlock + threadIdx.x;
+    const int rr = wb.y * kWeightRows + threadIdx.x;
     const bool active = rr < R.N;
     const size_t j = active ? (size_t)(a.rowkeys[R.off + rr] & 0xFFFFFull) : 0;
     const int2 wnd = a.win[R.rb0 + wb.y];
@@ -613,13 +615,13 @@ __global__ __launch_bounds__(kBlock) void bweights_kernel(BatchArgs a)
     if ((threadIdx.x & (kWave - 1)) == 0 && evaluated) atomicAdd(&a.st[wb.x].terms, evaluated);
 }
 
-__global__ __launch_bounds__(kBlock) void bfinalize_kernel(BatchArgs a)
+__global__ __launch_bounds__(kWeightRows) void bfinalize_kernel(BatchArgs a)
 {
     const int2 fb = a.fin_tab[blockIdx.x];
     const BRun& R = a.runs[fb.x];
     const BState& S = a.st[fb.x];
     if (S.failed) return;
-    const int j = fb.y * kBlock + threadIdx.x;
+    const int j = fb.y * kWeightRows + threadIdx.x;
     if (j >= R.N) return;
     double L = 0.0;
     for (int c = 0; c < R.wchunks; ++c) L += R.wpart[(size_t)c * R.N + j];
@@ -700,9 +702,10 @@ void batch_launch_stage(const BatchArgs& a, bool stage0, hipStream_t s)
         launch_sort_u64(a.colkeys, a.npad, s);
         launch_sort_u64(a.rowkeys, a.npad, s);
         hipLaunchKernelGGL(bcolgather_kernel, dim3((a.n_total + kBlock - 1) / kBlock), b, 0, s, a);
-        hipLaunchKernelGGL(bwindow_kernel, dim3(a.n_fin_blocks), b, 0, s, a);
-        hipLaunchKernelGGL(bweights_kernel, dim3(a.n_w_blocks), b, 0, s, a);
-        hipLaunchKernelGGL(bfinalize_kernel, dim3(a.n_fin_blocks), b, 0, s, a);
+        const dim3 bw(kWeightRows);
+        hipLaunchKernelGGL(bwindow_kernel, dim3(a.n_fin_blocks), bw, 0, s, a);
+        hipLaunchKernelGGL(bweights_kernel, dim3(a.n_w_blocks), bw, 0, s, a);
+        hipLaunchKernelGGL(bfinalize_kernel, dim3(a.n_fin_blocks), bw, 0, s, a);
     }
     hipLaunchKernelGGL(bnormalise_kernel, dim3(a.n_runs), b, 0, s, a, stage0 ? 1 : 0);
     hipLaunchKernelGGL(bselect_kernel, dim3(a.n_runs), b, 0, s, a);

@@ -94,7 +94,7 @@ RunLayout run_layout(const abcsmc_config& c, size_t o)
 
 // Batch-wide weight-window arrays after the tables: column and row sort keys
 // (power-of-two length), sorted columns, their sort-coordinate values, and
-// one window per 256-row block.
+// one window per kWeightRows-row block.
 struct WinLayout {
     size_t colkeys, rowkeys, scols, skey, rwin, win, end, npad;
 };
@@ -228,7 +228,7 @@ int apply_schedule(abcsmc_batch* b)
     for (int i = 0; i < b->R; ++i) {
         const int r = order[i];
         b->runs[r].wchunks = wchunks_for(b->cfgs[r].n_particles, s.weight_cols);
-        const int rb = (int)((b->cfgs[r].n_particles + kBlock - 1) / kBlock);
+        const int rb = (int)((b->cfgs[r].n_particles + kWeightRows - 1) / kWeightRows);
         for (int y = 0; y < rb; ++y)
             for (int c = 0; c < b->runs[r].wchunks; ++c) wt.push_back(make_int4(r, y, c, 0));
     }
@@ -333,8 +333,8 @@ int abcsmc_batch_workspace_size(const abcsmc_config* cfgs, int32_t n_runs, size_
         const RunLayout L = run_layout(cfgs[r], o);
         o = L.end;
         n_res += (int)((cfgs[r].n_particles + 1023) / 1024);
-        n_fin += (int)((cfgs[r].n_particles + kBlock - 1) / kBlock);
-        n_w += (int)((cfgs[r].n_particles + kBlock - 1) / kBlock) * wchunks_max(cfgs[r].n_particles);
+        n_fin += (int)((cfgs[r].n_particles + kWeightRows - 1) / kWeightRows);
+        n_w += (int)((cfgs[r].n_particles + kWeightRows - 1) / kWeightRows) * wchunks_max(cfgs[r].n_particles);
     }
     o = al(o + (size_t)n_runs * sizeof(BRun));
     o = al(o + (size_t)n_runs * sizeof(BState));
@@ -458,7 +458,7 @@ int abcsmc_batch_init(const abcsmc_config* cfgs, int32_t n_runs, const int64_t* 
         R.res_blk0 = (int32_t)res_tab.size();
         R.res_nblk = (int32_t)((c.n_particles + 1023) / 1024);
         for (int k = 0; k < R.res_nblk; ++k) res_tab.push_back(make_int2(r, k));
-        const int rb = (int)((c.n_particles + kBlock - 1) / kBlock);
+        const int rb = (int)((c.n_particles + kWeightRows - 1) / kWeightRows);
         for (int y = 0; y < rb; ++y) fin_tab.push_back(make_int2(r, y));
         b->max_w_blocks += rb * wchunks_max(c.n_particles);
         b->max_cap_chunks = std::max(b->max_cap_chunks, R.cap_chunks);

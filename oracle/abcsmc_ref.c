@@ -247,7 +247,10 @@ static double binv_recip(int64_t j)
     return tab[j];
 }
 
-int64_t ref_binomial(int64_t n, double p, uint64_t w)
+/* Bin(n, p) with the inversion uniform from word wu and, in the normal
+ * branch, the deviate from the Box-Muller pair of word wz (half 0: the
+ * cosine deviate, half 1: the sine deviate). */
+static int64_t binomial_core(int64_t n, double p, uint64_t wu, uint64_t wz, int half)
 {
     if (n <= 0 || p <= 0.0) return 0;
     if (p >= 1.0) return n;
@@ -260,7 +263,7 @@ int64_t ref_binomial(int64_t n, double p, uint64_t w)
         /* inversion by sequential search (BINV): F(k) accumulates the pmf,
          * f(k+1) = f(k) (n - k) r / (k + 1) with the division taken as a
          * product with the rounded reciprocal 1/(k+1) */
-        double u = ref_u01(w);
+        double u = ref_u01(wu);
         double f = ref_exp(dn * ref_log1p(-q));
         double F = f;
         double r = q / (1.0 - q);
@@ -273,8 +276,9 @@ int64_t ref_binomial(int64_t n, double p, uint64_t w)
         x = k;
     } else {
         /* normal approximation with continuity correction */
-        double z, z_unused;
-        ref_box_muller(w, &z, &z_unused);
+        double z0, z1;
+        ref_box_muller(wz, &z0, &z1);
+        double z = half ? z1 : z0;
         double sd = sqrt(m * (1.0 - q));
         double y = (m + 0.5) + sd * z;
         double fl = floor(y);
@@ -283,6 +287,12 @@ int64_t ref_binomial(int64_t n, double p, uint64_t w)
         x = (int64_t)fl;
     }
     return flip ? n - x : x;
+}
+
+/* One draw from one word: the uniform and the cosine deviate of the same word. */
+int64_t ref_binomial(int64_t n, double p, uint64_t w)
+{
+    return binomial_core(n, p, w, w, 0);
 }
 
 /* The paper's own transition sampler (§II-B): floor of a normal with mean
@@ -418,16 +428,19 @@ void ref_simulate(const ref_config* cfg, const double theta[REF_NPAR], const int
         else pw = ref_exp(n_exp * ref_log(C));
         double g = alpha0 + alpha_c / (1.0 + pw);
         double rate_si = (g * (double)I) * invP; /* per-susceptible rate g I / P */
-        uint64_t w[5];
-        for (uint32_t k = 0; k < 5; ++k) w[k] = ref_word(seed, index, round, REF_SIM, (uint32_t)t, k);
+        /* draw k: inversion uniform from word k; normal deviates in Box-Muller
+         * pairs: draws 0, 1 from word 5, draws 2, 3 from word 6, draw 4 from
+         * word 7 (the floor-normal sampler: the cosine deviate of word k) */
+        uint64_t w[8];
+        for (uint32_t k = 0; k < 8; ++k) w[k] = ref_word(seed, index, round, REF_SIM, (uint32_t)t, k);
         int64_t n1, n2, n3, n4, n5;
         if (cfg->sampler == 0) {
             double pSI = -ref_expm1(-rate_si);
-            n1 = ref_binomial(S, pSI, w[0]);
-            n2 = ref_binomial(I, pIA, w[1]);
-            n3 = ref_binomial(A, pAR, w[2]);
-            n4 = ref_binomial(A - n3, pAD, w[3]);
-            n5 = ref_binomial(I - n2, pIRu, w[4]);
+            n1 = binomial_core(S, pSI, w[0], w[5], 0);
+            n2 = binomial_core(I, pIA, w[1], w[5], 1);
+            n3 = binomial_core(A, pAR, w[2], w[6], 0);
+            n4 = binomial_core(A - n3, pAD, w[3], w[6], 1);
+            n5 = binomial_core(I - n2, pIRu, w[4], w[7], 0);
         } else {
             /* eq. 5 hazards h = (g S I/P, gamma I, beta A, delta A, beta eta I) */
             n1 = ref_normal_floor(S, rate_si * (double)S, w[0]);

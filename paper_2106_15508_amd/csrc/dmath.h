@@ -274,7 +274,7 @@ __device__ __forceinline__ void normal_pair(uint64_t w, double& z0, double& z1)
     z1 = rho * s;
 }
 
-// Cosine half of the pair only (the binomial's normal branch).
+// Cosine half of the pair only (the floor-normal and gamma samplers).
 __device__ __forceinline__ double normal_one(uint64_t w)
 {
     double z0, z1;
@@ -345,8 +345,12 @@ struct RecipTab {
 };
 __device__ constexpr RecipTab kRecip{};
 
-// Bin(n, p) from one word; n is an exact integer held in a double.
-__device__ __forceinline__ double binomial(double n, double p, uint64_t w)
+// Bin(n, p) with the inversion uniform from word wu and, in the normal
+// branch, the deviate of the Box-Muller pair of word wz (half 0: cosine,
+// half 1: sine), formed on first use and kept in (have, z0, z1) for the
+// draw that shares the pair; n is an exact integer held in a double.
+__device__ __forceinline__ double binomial_pair(double n, double p, uint64_t wu, uint64_t wz, int half, bool& have,
+                                                double& z0, double& z1)
 {
     if (n <= 0.0 || p <= 0.0) return 0.0;
     if (p >= 1.0) return n;
@@ -355,7 +359,7 @@ __device__ __forceinline__ double binomial(double n, double p, uint64_t w)
     const double m = n * q;
     double x;
     if (m < kTSwitch) {
-        const double u = u01(w);
+        const double u = u01(wu);
         double f = exp(n * log1p(-q));
         double F = f;
         const double r = q / (1.0 - q);
@@ -367,7 +371,11 @@ __device__ __forceinline__ double binomial(double n, double p, uint64_t w)
         }
         x = k;
     } else {
-        const double z = normal_one(w);
+        if (!have) {
+            normal_pair(wz, z0, z1);
+            have = true;
+        }
+        const double z = half ? z1 : z0;
         const double sd = __builtin_sqrt(m * (1.0 - q));
         const double y = (m + 0.5) + sd * z;
         x = __builtin_floor(y);
@@ -375,6 +383,14 @@ __device__ __forceinline__ double binomial(double n, double p, uint64_t w)
         if (x > n) x = n;
     }
     return flip ? n - x : x;
+}
+
+// Bin(n, p) from one word: its uniform and its cosine deviate.
+__device__ __forceinline__ double binomial(double n, double p, uint64_t w)
+{
+    bool have = false;
+    double z0, z1;
+    return binomial_pair(n, p, w, w, 0, have, z0, z1);
 }
 
 // floor(N(h, sqrt h)) clamped to [0, n] (the paper's own transition sampler).

@@ -18,8 +18,10 @@ namespace lane {
 //          each drawn from what is left of its source compartment
 //   dist   sum over days 1..T of dA^2, dR^2, dD^2 in that order; sqrt at the end
 // Returns +inf as soon as the partial sum exceeds exit_thr (the final
-// distance would exceed eps).  Draw k of day t is word k of the stream
-// (index, round, SIM, t): blocks 0, 0, 1, 1, 2.
+// distance would exceed eps).  Stream (index, round, SIM, t) of day t: draw k
+// takes its inversion uniform from word k and its normal deviate from the
+// Box-Muller pairs of words 5 (draws 0, 1), 6 (draws 2, 3) and 7 (draw 4);
+// the floor-normal sampler uses the cosine deviate of word k.
 // ---------------------------------------------------------------------------
 // With kSplit the three series' sums of squares also go to split[0..2]
 // (no early exit; the surrogate's training targets); the returned distance
@@ -73,11 +75,14 @@ __device__ __forceinline__ double simulate_distance(const Model& m, const double
         double n1, n2, n3, n4, n5;
         if (kSampler == 0) {
             const double pSI = -dm::expm1(-rate);
-            n1 = dm::binomial(S, pSI, b0.a);
-            n2 = dm::binomial(I, pIA, b0.b);
-            n3 = dm::binomial(A, pAR, b1.a);
-            n4 = dm::binomial(A - n3, pAD, b1.b);
-            n5 = dm::binomial(I - n2, pIRu, b2.a);
+            const dm::w2 b3 = dm::block_words(m.seed, index, round, dm::kSim, (uint32_t)t, 3);
+            bool h01 = false, h23 = false, h4 = false;
+            double z0, z1, z2, z3, z4, z5;
+            n1 = dm::binomial_pair(S, pSI, b0.a, b2.b, 0, h01, z0, z1);
+            n2 = dm::binomial_pair(I, pIA, b0.b, b2.b, 1, h01, z0, z1);
+            n3 = dm::binomial_pair(A, pAR, b1.a, b3.a, 0, h23, z2, z3);
+            n4 = dm::binomial_pair(A - n3, pAD, b1.b, b3.a, 1, h23, z2, z3);
+            n5 = dm::binomial_pair(I - n2, pIRu, b2.a, b3.b, 0, h4, z4, z5);
         } else {
             n1 = dm::normal_floor(S, rate * S, b0.a);
             n2 = dm::normal_floor(I, gamma * I, b0.b);

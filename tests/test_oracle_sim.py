@@ -165,3 +165,26 @@ def test_normal_floor_sampler_properties(oracle):
         tr = oracle.simulate(w, W.THETA_TRUE, 8, 1, i, obs0=(1000, 0, 0))
         assert np.all(tr.sum(1) == w.population) and np.all(tr >= 0)
         assert np.all(np.diff(tr[:, 3]) >= 0)
+
+
+def test_paired_normal_draws_are_uncorrelated(oracle):
+    """Draws 0 and 1 (and 2 and 3) of a day take the cosine and sine deviates
+    of one Box-Muller pair: in the normal branch their counts must still be
+    independent (reusing one deviate, or a sign-flipped copy, gives a
+    correlation of +-1)."""
+    P, A0 = 10_000_000, 50_000
+    w = W.C2.with_(n_days=1)
+    th = (0.3, 2.0, 0.5, 0.05, 0.1, 0.005, 0.2, 1.0)
+    cnt = 4000
+    tr = np.stack([oracle.simulate(w, th, 5, 2, i, obs0=(A0, 0, 0)) for i in range(cnt)]).astype(np.float64)
+    S0, I0 = tr[0, 0, 0], tr[0, 0, 1]
+    n1 = S0 - tr[:, 1, 0]
+    n3, n4, n5 = tr[:, 1, 3], tr[:, 1, 4], tr[:, 1, 5]
+    n2 = tr[:, 1, 2] - A0 + n3 + n4
+    assert np.all(tr[:, 1, 1] == I0 + n1 - n2 - n5)
+    lim = 4.0 / math.sqrt(cnt)
+    assert abs(np.corrcoef(n1, n2)[0, 1]) < lim
+    # n4 ~ Bin(A - n3, p_AD): its mean moves with n3 by -p_AD (a correlation of about -0.02)
+    assert abs(np.corrcoef(n3, n4)[0, 1]) < lim
+    for x in (n1, n2, n3, n4):
+        assert x.std() > 5.0   # all four in the normal branch

@@ -131,12 +131,13 @@ typedef struct {
     int64_t batches;              /* batches launched */
     double ms_resample, ms_simulate, ms_weights, ms_select, ms_total; /* device time per phase */
     double ms_k_propose;          /* summed device time of the proposal kernel launches */
-    double ms_k_weights;          /* device time of the importance-weight kernel */
+    double ms_k_weights;          /* device time of the importance-weight sum kernel (without the window
+                                     pass before it and the merge of chunk sums after it) */
     int64_t n_k_propose;          /* proposal kernel launches (= batches) */
     int64_t sim_days;             /* proposal-days simulated (early exit stops counting) */
     int64_t weight_pairs;         /* N x survivors terms of the importance-weight sums */
     int64_t weight_terms;         /* terms actually evaluated (the rest lie outside every row's window,
-                                     which bounds their total by 2^-64 of the row sum) */
+                                     which bounds their total by 2^-53 of the row sum) */
     double mcmc_s;                /* STEP_MCMC: step size after this stage (0 otherwise) */
     double beta_b_real;           /* Beta shape b as a real number (STEP_MEANVAR / STEP_MODECONC) */
 } abcsmc_round_info;

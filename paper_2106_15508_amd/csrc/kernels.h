@@ -191,7 +191,12 @@ struct TrajArgs {
 void launch_propose(const ProposeArgs& a, bool round0, hipStream_t s);
 void launch_compact(const CompactArgs& a, hipStream_t s);
 void launch_resample(const ResampleArgs& a, hipStream_t s);
-void launch_weights(const WeightArgs& a, hipStream_t s);
+// The weight pass in three parts, so that the caller can time the sum kernel
+// alone: the window pass (coordinate pick, column and row sorts, windows),
+// the windowed sums, and the per-row merge of the chunk partial sums.
+void launch_weights_window(const WeightArgs& a, hipStream_t s);
+void launch_weights_sum(const WeightArgs& a, hipStream_t s);
+void launch_weights_finalize(const WeightArgs& a, hipStream_t s);
 void launch_normalise(const NormArgs& a, hipStream_t s);
 void launch_select(const SelectArgs& a, hipStream_t s);
 void launch_uniform_weights(double* W, double* logw, int32_t N, hipStream_t s);

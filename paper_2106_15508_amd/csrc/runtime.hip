@@ -496,10 +496,14 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
         wa.n_prev = N;
         wa.rwin = x->at<double>(x->L.rwin);
         weight_exp_constants(wa.ex);
+        launch_weights_window(wa, s);
+        HIPCHK(x, hipGetLastError());
         HIPCHK(x, hipEventRecord(x->ev[7], s));
-        launch_weights(wa, s);
+        launch_weights_sum(wa, s);
         HIPCHK(x, hipGetLastError());
         HIPCHK(x, hipEventRecord(x->ev[8], s));
+        launch_weights_finalize(wa, s);
+        HIPCHK(x, hipGetLastError());
         if (screened) {
             const int rc = surrogate_weights(x, dst, nxt);
             if (rc) return rc;

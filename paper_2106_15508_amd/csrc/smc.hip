@@ -243,7 +243,7 @@ using wterm::wave_min;
 // Row j only needs the columns whose coordinate d* lies within its
 // half-width R_j = W_j sigma_j of u_jd*: every other column has a term at
 // most q_k e^{-W_j^2/2}, and W_j is chosen from the row's own parent term so
-// that all of them together stay below 2^-64 of the row sum (at most 37.7,
+// that all of them together stay below 2^-53 of the row sum (at most 37.7,
 // where every omitted exponential is below e^-710).  Per stage: pick the
 // coordinate d* with the largest spread among the columns (the windows then
 // exclude the most columns: sigma is the same in every coordinate), sort the
@@ -669,7 +669,7 @@ void launch_resample(const ResampleArgs& a, hipStream_t s)
     hipLaunchKernelGGL(resample_write_kernel, g, b, 0, s, a);
 }
 
-void launch_weights(const WeightArgs& a, hipStream_t s)
+void launch_weights_window(const WeightArgs& a, hipStream_t s)
 {
     const dim3 b(kBlock);
     const unsigned gp = blocks_of((int64_t)a.npad, kBlock);
@@ -681,8 +681,16 @@ void launch_weights(const WeightArgs& a, hipStream_t s)
     hipLaunchKernelGGL(wrowkeys_kernel, dim3(gp), b, 0, s, a);
     launch_sort_u64(a.rowkeys, a.npad, s);
     hipLaunchKernelGGL(wwindow_kernel, dim3(blocks_of(a.N, kWeightRows)), dim3(kWeightRows), 0, s, a);
+}
+
+void launch_weights_sum(const WeightArgs& a, hipStream_t s)
+{
     hipLaunchKernelGGL(weights_kernel, dim3(blocks_of(a.N, kWeightRows), a.chunks), dim3(kWeightRows), 0, s, a);
-    hipLaunchKernelGGL(weights_finalize_kernel, dim3(blocks_of(a.N, kBlock)), b, 0, s, a);
+}
+
+void launch_weights_finalize(const WeightArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(weights_finalize_kernel, dim3(blocks_of(a.N, kBlock)), dim3(kBlock), 0, s, a);
 }
 
 // Columns per chunk (grid y) of a row block's window: at most 128 chunks of at

@@ -126,9 +126,9 @@ constexpr double kWindow = 37.7;
 // q_k e^{-W^2/2}, so all of them together are at most Q e^{-W^2/2}
 // (Q = sum_k q_k).  The row sum holds the parent's own term
 // L_par = q_par e^{-|u_j - u_par|^2 / (2 sigma_j^2)}, so with
-//   W^2 = 2 (ln Q - ln L_par + 64 ln 2)
-// the omitted mass is at most 2^-64 of the row sum -- below the rounding of
-// the sum itself.  The parent always lies inside (W^2 >= |u_j - u_par|^2 /
+//   W^2 = 2 (ln Q - ln L_par + 53 ln 2)
+// the omitted mass is at most 2^-53 of the row sum: one unit roundoff of the
+// sum itself.  The parent always lies inside (W^2 >= |u_j - u_par|^2 /
 // sigma_j^2 because Q >= q_par).  The result is capped at kWindow; a missing
 // or zero parent weight leaves kWindow.  Returns the half-width W sigma_j.
 __device__ __forceinline__ double window_halfwidth(const double* uj, double sj, const double* up, double qpar,
@@ -143,7 +143,7 @@ __device__ __forceinline__ double window_halfwidth(const double* uj, double sj, 
             d2 = d2 + e * e;
         }
         const double x = d2 / (2.0 * sj * sj);
-        const double w2 = 2.0 * ((dm::log(Q) - dm::log(qpar)) + x + 64.0 * 0.6931471805599453);
+        const double w2 = 2.0 * ((dm::log(Q) - dm::log(qpar)) + x + 53.0 * 0.6931471805599453);
         const double w = __builtin_sqrt(w2);
         if (w < W) W = w;
     }

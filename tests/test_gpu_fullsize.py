@@ -4,7 +4,8 @@ workspace and stream, early exit on, library-chosen batches).
 C2 (P=1e7, T=120, N=131072): stages 0 and 1 are recomputed completely by the
 oracle (process pool) and compared bit for bit, including eps^1 and eps^2;
 importance weights on sampled rows within 1e-12.  C3 (P=3e8, T=180,
-N=2^20): sampled stage-0 particles bit for bit, invariants of stage 1.  C5
+N=2^20) and the largest population the library accepts (N=2^22): sampled
+stage-0 particles bit for bit, invariants of stage 1.  C5
 (C2 with the learned screen at the benchmark's settings): sampled
 acceptances of the first screened stage against the oracle."""
 import numpy as np
@@ -82,24 +83,25 @@ def test_c2_stages_0_1_bitwise(oracle):
     assert np.all(g[1]["W"] >= 0)
 
 
-def test_c3_sampled_and_invariants(oracle):
-    w = W.C3
+def _check_stage0_sampled(oracle, w, obs, g, seed, n_sample):
     N = w.n_particles
-    obs = oracle.observations(w)
-    g = _gpu_stages(w, obs, 2)
-    rng = np.random.default_rng(3)
-    for j in np.unique(np.concatenate([[0, 1, N - 1], rng.integers(0, N, 200)])):
+    rng = np.random.default_rng(seed)
+    for j in np.unique(np.concatenate([[0, 1, N - 1], rng.integers(0, N, n_sample)])):
         u = oracle.prior_draw(w, int(j))
         assert np.array_equal(_bits(g[0]["u"][j]), _bits(u)), j
         assert _bits([g[0]["d"][j]])[0] == _bits([oracle.sim_distance(w, obs, u, 0, int(j))])[0], j
     # eps^1 is the linear-interpolation median of the stage-0 distances (numpy)
     assert g[0]["info"]["eps_next"] == np.quantile(g[0]["d"], w.surv_ratio, method="linear")
+
+
+def _check_stage1_invariants(w, g):
     st = g[1]
     eps1 = st["info"]["eps"]
     assert np.all(st["d"] <= eps1)
     assert np.all(np.diff(st["index"]) > 0)
     assert st["index"][-1] == st["info"]["proposals"] - 1
     assert np.all((st["u"] >= 0) & (st["u"] <= 1))
+    assert np.all(st["W"] >= 0) and np.all(np.isfinite(st["logw"]))
     assert abs(st["W"].sum() - 1.0) < 1e-12
     assert st["info"]["eps_next"] == np.quantile(st["d"], w.surv_ratio, method="linear")
     # the integer CDF is the running sum of the quantised eq. 10 weights: zero
@@ -110,6 +112,29 @@ def test_c3_sampled_and_invariants(oracle):
     assert q.max() == 2**40 and q[np.argmin(d0)] == 2**40
     assert np.array_equal(cdf, np.cumsum(q.astype(object)).astype(np.uint64))
     assert st["info"]["survivors"] == int(np.count_nonzero(q))
+    # every parent drawn is a survivor of stage 0 (eq. 11 has no mass elsewhere)
+    assert np.all(q[st["parent"]] > 0)
+
+
+def test_c3_sampled_and_invariants(oracle):
+    w = W.C3
+    obs = oracle.observations(w)
+    g = _gpu_stages(w, obs, 2)
+    _check_stage0_sampled(oracle, w, obs, g, 3, 200)
+    _check_stage1_invariants(w, g)
+
+
+def test_largest_population_sampled_and_invariants(oracle):
+    """N = 2^22, the largest population the library accepts (the integer CDF
+    of eq. 10 weights, at most 2^40 each, then still fits 64 bits): sampled
+    stage-0 particles bit for bit against the oracle, invariants of stage 1
+    (its importance weights over 2^22 x survivors terms included)."""
+    w = W.C2.with_(n_particles=1 << 22, population=1_000_000, n_days=40, n_rounds=2)
+    obs = oracle.observations(w)
+    g = _gpu_stages(w, obs, 2)
+    assert len(g[0]["d"]) == len(g[1]["d"]) == 1 << 22
+    _check_stage0_sampled(oracle, w, obs, g, 4, 100)
+    _check_stage1_invariants(w, g)
 
 
 def test_c5_screened_stage_sampled(oracle):

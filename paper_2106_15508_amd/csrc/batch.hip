@@ -699,8 +699,7 @@ void batch_launch_stage(const BatchArgs& a, bool stage0, hipStream_t s)
     if (!stage0) {
         hipLaunchKernelGGL(bwdim_kernel, dim3(a.n_runs), b, 0, s, a);
         hipLaunchKernelGGL(bkeys_kernel, dim3(a.n_key_blocks), b, 0, s, a);
-        launch_sort_u64(a.colkeys, a.npad, s);
-        launch_sort_u64(a.rowkeys, a.npad, s);
+        launch_sort_u64_pair(a.colkeys, a.rowkeys, a.npad, s);
         hipLaunchKernelGGL(bcolgather_kernel, dim3((a.n_total + kBlock - 1) / kBlock), b, 0, s, a);
         const dim3 bw(kWeightRows);
         hipLaunchKernelGGL(bwindow_kernel, dim3(a.n_fin_blocks), bw, 0, s, a);

@@ -155,6 +155,8 @@ void weight_exp_constants(double ex[7]);
 // Bitonic sort of 64-bit keys (length a power of two >= 2048).
 size_t sort_padded_size(size_t n);
 void launch_sort_u64(unsigned long long* keys, size_t n_pow2, hipStream_t s);
+// both arrays (each n_pow2 keys; keys1 may be null) by the same launches
+void launch_sort_u64_pair(unsigned long long* keys0, unsigned long long* keys1, size_t n_pow2, hipStream_t s);
 
 struct NormArgs {
     const double* logw;

@@ -676,10 +676,9 @@ void launch_weights_window(const WeightArgs& a, hipStream_t s)
     hipLaunchKernelGGL(wdim_partial_kernel, dim3(kDimBlocks), b, 0, s, a);
     hipLaunchKernelGGL(wdim_pick_kernel, dim3(1), b, 0, s, a);
     hipLaunchKernelGGL(wcolkeys_kernel, dim3(gp), b, 0, s, a);
-    launch_sort_u64(a.colkeys, a.npad, s);
-    hipLaunchKernelGGL(wcolgather_kernel, dim3(blocks_of(a.N, kBlock)), b, 0, s, a);
     hipLaunchKernelGGL(wrowkeys_kernel, dim3(gp), b, 0, s, a);
-    launch_sort_u64(a.rowkeys, a.npad, s);
+    launch_sort_u64_pair(a.colkeys, a.rowkeys, a.npad, s);
+    hipLaunchKernelGGL(wcolgather_kernel, dim3(blocks_of(a.N, kBlock)), b, 0, s, a);
     hipLaunchKernelGGL(wwindow_kernel, dim3(blocks_of(a.N, kWeightRows)), dim3(kWeightRows), 0, s, a);
 }
 

@@ -1,7 +1,9 @@
 // sort.hip -- ascending bitonic sort of 64-bit keys in place (power-of-two
 // length, pad with UINT64_MAX).  Callers make keys unique (payload index in
 // the low bits), so the order is fully determined.  Strides below 2048 run
-// inside LDS; larger strides are one compare-exchange per thread per launch.
+// inside LDS; larger strides run two per launch where they can (four keys per
+// thread).  Two arrays of the same length can be sorted by the same launches
+// (grid.y selects the array), which halves the launches of the weight pass.
 #include "kernels.h"
 
 namespace abcsmc {
@@ -22,9 +24,10 @@ __device__ __forceinline__ void cmpx(unsigned long long& a, unsigned long long& 
 
 // Every bitonic stage up to the tile size (k = 2 .. 2048), directions taken
 // from the global index so tiles combine into the global network.
-__global__ __launch_bounds__(kSortThreads) void bitonic_tile_kernel(unsigned long long* keys)
+__global__ __launch_bounds__(kSortThreads) void bitonic_tile_kernel(unsigned long long* keys0, unsigned long long* keys1)
 {
     __shared__ unsigned long long s[kSortTile];
+    unsigned long long* keys = blockIdx.y ? keys1 : keys0;
     const size_t base = (size_t)blockIdx.x * kSortTile;
     s[threadIdx.x] = keys[base + threadIdx.x];
     s[threadIdx.x + kSortThreads] = keys[base + threadIdx.x + kSortThreads];
@@ -43,9 +46,11 @@ __global__ __launch_bounds__(kSortThreads) void bitonic_tile_kernel(unsigned lon
 }
 
 // Strides j < 2048 of stage k (k > 2048) inside LDS.
-__global__ __launch_bounds__(kSortThreads) void bitonic_merge_tile_kernel(unsigned long long* keys, size_t k)
+__global__ __launch_bounds__(kSortThreads) void bitonic_merge_tile_kernel(unsigned long long* keys0,
+                                                                         unsigned long long* keys1, size_t k)
 {
     __shared__ unsigned long long s[kSortTile];
+    unsigned long long* keys = blockIdx.y ? keys1 : keys0;
     const size_t base = (size_t)blockIdx.x * kSortTile;
     s[threadIdx.x] = keys[base + threadIdx.x];
     s[threadIdx.x + kSortThreads] = keys[base + threadIdx.x + kSortThreads];
@@ -62,8 +67,10 @@ __global__ __launch_bounds__(kSortThreads) void bitonic_merge_tile_kernel(unsign
 }
 
 // One global compare-exchange step (stage k, stride j >= 2048).
-__global__ __launch_bounds__(kBlock) void bitonic_step_kernel(unsigned long long* keys, size_t n, size_t k, size_t j)
+__global__ __launch_bounds__(kBlock) void bitonic_step_kernel(unsigned long long* keys0, unsigned long long* keys1,
+                                                              size_t n, size_t k, size_t j)
 {
+    unsigned long long* keys = blockIdx.y ? keys1 : keys0;
     const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= n / 2) return;
     const size_t i = (t / j) * 2 * j + (t % j);
@@ -71,6 +78,31 @@ __global__ __launch_bounds__(kBlock) void bitonic_step_kernel(unsigned long long
     cmpx(a, b, (i & k) == 0);
     keys[i] = a;
     keys[i + j] = b;
+}
+
+// Two consecutive global steps of stage k, strides j and h = j/2 (h >= 2048):
+// thread t owns the keys i, i + h, i + j, i + j + h with i = (t / h) 2j + t % h,
+// all in one 2j-block and so in one k-block (2j <= k): the stride-j pairs
+// (i, i + j), (i + h, i + j + h), then the stride-h pairs (i, i + h),
+// (i + j, i + j + h).  Every key belongs to exactly one thread.
+__global__ __launch_bounds__(kBlock) void bitonic_step2_kernel(unsigned long long* keys0, unsigned long long* keys1,
+                                                               size_t n, size_t k, size_t j)
+{
+    unsigned long long* keys = blockIdx.y ? keys1 : keys0;
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n / 4) return;
+    const size_t h = j >> 1;
+    const size_t i = (t / h) * 2 * j + (t % h);
+    unsigned long long a = keys[i], b = keys[i + h], c = keys[i + j], d = keys[i + j + h];
+    const bool up = (i & k) == 0;
+    cmpx(a, c, up);
+    cmpx(b, d, up);
+    cmpx(a, b, up);
+    cmpx(c, d, up);
+    keys[i] = a;
+    keys[i + h] = b;
+    keys[i + j] = c;
+    keys[i + j + h] = d;
 }
 
 }  // namespace
@@ -82,16 +114,26 @@ size_t sort_padded_size(size_t n)
     return p;
 }
 
-void launch_sort_u64(unsigned long long* keys, size_t n_pow2, hipStream_t s)
+void launch_sort_u64_pair(unsigned long long* keys0, unsigned long long* keys1, size_t n_pow2, hipStream_t s)
 {
     const unsigned tiles = (unsigned)(n_pow2 / kSortTile);
-    hipLaunchKernelGGL(bitonic_tile_kernel, dim3(tiles), dim3(kSortThreads), 0, s, keys);
+    const unsigned arrays = keys1 ? 2u : 1u;
+    const dim3 bt(kSortThreads), bs(kBlock);
+    const dim3 g1((unsigned)((n_pow2 / 2 + kBlock - 1) / kBlock), arrays);
+    const dim3 g2((unsigned)((n_pow2 / 4 + kBlock - 1) / kBlock), arrays);
+    hipLaunchKernelGGL(bitonic_tile_kernel, dim3(tiles, arrays), bt, 0, s, keys0, keys1);
     for (size_t k = (size_t)kSortTile << 1; k <= n_pow2; k <<= 1) {
-        for (size_t j = k >> 1; j >= (size_t)kSortTile; j >>= 1)
-            hipLaunchKernelGGL(bitonic_step_kernel, dim3((unsigned)((n_pow2 / 2 + kBlock - 1) / kBlock)), dim3(kBlock),
-                               0, s, keys, n_pow2, k, j);
-        hipLaunchKernelGGL(bitonic_merge_tile_kernel, dim3(tiles), dim3(kSortThreads), 0, s, keys, k);
+        size_t j = k >> 1;
+        for (; j >= 2 * (size_t)kSortTile; j >>= 2)
+            hipLaunchKernelGGL(bitonic_step2_kernel, g2, bs, 0, s, keys0, keys1, n_pow2, k, j);
+        if (j >= (size_t)kSortTile) hipLaunchKernelGGL(bitonic_step_kernel, g1, bs, 0, s, keys0, keys1, n_pow2, k, j);
+        hipLaunchKernelGGL(bitonic_merge_tile_kernel, dim3(tiles, arrays), bt, 0, s, keys0, keys1, k);
     }
+}
+
+void launch_sort_u64(unsigned long long* keys, size_t n_pow2, hipStream_t s)
+{
+    launch_sort_u64_pair(keys, nullptr, n_pow2, s);
 }
 
 }  // namespace abcsmc

@@ -100,6 +100,7 @@ struct BatchArgs {
     double* skey;              // n_total sorted sort-coordinate values
     double* rwin;              // n_total per-row window half-widths (slot off_r + j)
     int2* win;                 // per 128-row block: column window [x, y) within the run
+    const double* wtab;        // kWeightTab entries 2^(i/1024) of the table exponential
     size_t npad;               // power-of-two sort length >= n_total
     int32_t n_total;           // sum of N_r
     int32_t n_key_blocks;      // ceil(npad / 256)

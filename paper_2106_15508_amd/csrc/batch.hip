@@ -589,7 +589,7 @@ __global__ __launch_bounds__(kWeightRows) void bweights_kernel(BatchArgs a)
         if (active) R.wpart[(size_t)c * R.N + j] = 0.0;
         return;
     }
-    wterm::fill_table(T);
+    wterm::load_table(T, a.wtab);
     __syncthreads();
     const int ds = S.dstar;
     double uj[kNP];

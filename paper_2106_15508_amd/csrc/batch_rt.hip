@@ -93,10 +93,10 @@ RunLayout run_layout(const abcsmc_config& c, size_t o)
 }
 
 // Batch-wide weight-window arrays after the tables: column and row sort keys
-// (power-of-two length), sorted columns, their sort-coordinate values, and
-// one window per kWeightRows-row block.
+// (power-of-two length), sorted columns, their sort-coordinate values, one
+// window per kWeightRows-row block, and the exponential table.
 struct WinLayout {
-    size_t colkeys, rowkeys, scols, skey, rwin, win, end, npad;
+    size_t colkeys, rowkeys, scols, skey, rwin, win, wtab, end, npad;
 };
 
 WinLayout win_layout(size_t o, size_t n_total, size_t n_fin)
@@ -114,6 +114,7 @@ WinLayout win_layout(size_t o, size_t n_total, size_t n_fin)
     L.skey = take(n_total * 8);
     L.rwin = take(n_total * 8);
     L.win = take(n_fin * sizeof(int2));
+    L.wtab = take(kWeightTab * 8);
     L.end = o;
     return L;
 }
@@ -507,6 +508,9 @@ int abcsmc_batch_init(const abcsmc_config* cfgs, int32_t n_runs, const int64_t* 
     A.skey = (double*)(b->ws + WL.skey);
     A.rwin = (double*)(b->ws + WL.rwin);
     A.win = (int2*)(b->ws + WL.win);
+    A.wtab = (const double*)(b->ws + WL.wtab);
+    launch_weight_table((double*)(b->ws + WL.wtab), b->stream);
+    if (hipGetLastError() != hipSuccess) return bail(ABCSMC_EDEVICE, "launch of the exponential table failed");
     A.npad = WL.npad;
     A.n_total = (int32_t)n_total;
     A.n_key_blocks = (int32_t)((WL.npad + kBlock - 1) / kBlock);

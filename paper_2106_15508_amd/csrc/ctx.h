@@ -31,7 +31,7 @@ struct DevPop {
 // Byte layout of the device workspace (every region 256-byte aligned).
 struct Layout {
     size_t obs, pop[2][8], q, cdf, cols, st_u, st_d, st_sigma, st_parent, st_att, wave_mask, wave_off,
-        ctr, scal, theta, red[5], hist, sel, wpart, rowkeys, colkeys, scols, skey, dimpart, dstar, win, rwin, total;
+        ctr, scal, theta, red[5], hist, sel, wpart, rowkeys, colkeys, scols, skey, dimpart, dstar, win, rwin, wtab, total;
 };
 
 inline int fail(std::string* where, int code, const std::string& msg)

@@ -115,6 +115,9 @@ struct ResampleArgs {
     StageCounters* ctr;
 };
 
+// Entries of the weight kernels' exponential table (2^(i/1024)).
+constexpr int kWeightTab = 1024;
+
 struct WeightArgs {
     const double* u;        // N x 8 rows
     const double* sigma;    // N
@@ -147,10 +150,13 @@ struct WeightArgs {
     // table exponential: ln2/1024, its square / 2, its cube / 6, 1024/ln2
     // (kernel arguments so they sit in scalar registers)
     double ex[7];
+    const double* tab;      // kWeightTab entries 2^(i/1024), written once per context
 };
 
 // Fill WeightArgs::ex.
 void weight_exp_constants(double ex[7]);
+// Write the kWeightTab table entries 2^(i/1024) to tab (device memory).
+void launch_weight_table(double* tab, hipStream_t s);
 
 // Bitonic sort of 64-bit keys (length a power of two >= 2048).
 size_t sort_padded_size(size_t n);

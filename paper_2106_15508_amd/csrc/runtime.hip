@@ -86,6 +86,7 @@ Layout make_layout(const abcsmc_config& c)
     L.dstar = take(sizeof(int32_t));
     L.win = take(((N + kWeightRows - 1) / kWeightRows) * sizeof(int2));
     L.rwin = take(N * sizeof(double));
+    L.wtab = take(kWeightTab * sizeof(double));
     L.total = o;
     return L;
 }
@@ -280,10 +281,12 @@ int abcsmc_init(const abcsmc_config* cfg, const int64_t* obs, abcsmc_ctx** out)
             return bail(ABCSMC_EDEVICE);
         }
     std::vector<double> od(x->obs.begin(), x->obs.end());
-    if (hipMemcpyAsync(x->at<double>(x->L.obs), od.data(), od.size() * sizeof(double), hipMemcpyHostToDevice,
+    launch_weight_table(x->at<double>(x->L.wtab), x->stream);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(x->at<double>(x->L.obs), od.data(), od.size() * sizeof(double), hipMemcpyHostToDevice,
                        x->stream) != hipSuccess ||
         hipStreamSynchronize(x->stream) != hipSuccess) {
-        x->err = "copy of the observations failed";
+        x->err = "set-up of the exponential table or copy of the observations failed";
         return bail(ABCSMC_EDEVICE);
     }
     *out = x;
@@ -495,6 +498,7 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
         wa.cdf = x->at<uint64_t>(x->L.cdf);
         wa.n_prev = N;
         wa.rwin = x->at<double>(x->L.rwin);
+        wa.tab = x->at<double>(x->L.wtab);
         weight_exp_constants(wa.ex);
         launch_weights_window(wa, s);
         HIPCHK(x, hipGetLastError());

@@ -389,7 +389,7 @@ __global__ __launch_bounds__(kWeightRows) void weights_kernel(WeightArgs a)
     const int k0 = wnd.x + (int)blockIdx.y * a.cols_per_chunk;
     const int k1 = min(wnd.y, k0 + a.cols_per_chunk);
     if (k0 >= k1) return;  // past the window: the finalize pass does not read this chunk
-    wterm::fill_table(T);
+    wterm::load_table(T, a.tab);
     __syncthreads();
     const int ds = *a.dstar;
     double uj[kNP];
@@ -416,6 +416,12 @@ __global__ __launch_bounds__(kWeightRows) void weights_kernel(WeightArgs a)
                                         k1, wlo, whi, T, a.ex, lanes, evaluated);
     if (active) a.partial[(size_t)blockIdx.y * a.N + r] = total;
     if ((threadIdx.x & (kWave - 1)) == 0 && evaluated) atomicAdd(a.terms, evaluated);
+}
+
+__global__ __launch_bounds__(kBlock) void wtable_kernel(double* tab)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < wterm::kTab) tab[i] = wterm::table_entry(i);
 }
 
 __global__ __launch_bounds__(kBlock) void weights_finalize_kernel(WeightArgs a)
@@ -680,6 +686,11 @@ void launch_weights_window(const WeightArgs& a, hipStream_t s)
     launch_sort_u64_pair(a.colkeys, a.rowkeys, a.npad, s);
     hipLaunchKernelGGL(wcolgather_kernel, dim3(blocks_of(a.N, kBlock)), b, 0, s, a);
     hipLaunchKernelGGL(wwindow_kernel, dim3(blocks_of(a.N, kWeightRows)), dim3(kWeightRows), 0, s, a);
+}
+
+void launch_weight_table(double* tab, hipStream_t s)
+{
+    hipLaunchKernelGGL(wtable_kernel, dim3((wterm::kTab + kBlock - 1) / kBlock), dim3(kBlock), 0, s, tab);
 }
 
 void launch_weights_sum(const WeightArgs& a, hipStream_t s)

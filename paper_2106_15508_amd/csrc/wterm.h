@@ -72,10 +72,19 @@ __device__ __forceinline__ double row_scale(double sigma, const double* ex)
     return -ex[3] / (2.0 * (sigma * sigma));
 }
 
-// 2^(i/1024), i = 0..1023, into LDS (all threads of the block take part).
-__device__ __forceinline__ void fill_table(double* T)
+static_assert(kTab == kWeightTab, "table length");
+
+// Table entry i: 2^(i/1024).
+__device__ __forceinline__ double table_entry(int i)
 {
-    for (int i = threadIdx.x; i < kTab; i += blockDim.x) T[i] = dm::exp((double)i * (0.6931471805599453 / kTab));
+    return dm::exp((double)i * (0.6931471805599453 / kTab));
+}
+
+// Copy of the table (written once per context by launch_weight_table) into
+// LDS; all threads of the block take part.
+__device__ __forceinline__ void load_table(double* T, const double* g)
+{
+    for (int i = threadIdx.x; i < kTab; i += blockDim.x) T[i] = g[i];
 }
 
 // Sum over the sorted columns [k0, k1) for this lane's row, in 256-column

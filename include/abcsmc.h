@@ -145,7 +145,9 @@ typedef struct {
 typedef struct abcsmc_ctx abcsmc_ctx;
 
 /* Device bytes a context needs for cfg (the workspace, if supplied, must be
- * at least this large). */
+ * at least this large, 256-byte aligned, and left to the context until
+ * abcsmc_free: it holds the populations between stages and tables written
+ * once at abcsmc_init). */
 int abcsmc_workspace_size(const abcsmc_config* cfg, size_t* bytes);
 
 /* Create a context.  obs: (T+1) x 3 int64, row t = (A, R, D) on day t, row 0

@@ -95,7 +95,7 @@ struct BatchArgs {
     double ex[7];              // table-exp constants (as WeightArgs::ex)
     // weight window (batch-wide arrays; run r owns slots [off_r, off_r + N_r))
     unsigned long long* colkeys;  // npad: (run, column key, column) sorted
-    unsigned long long* rowkeys;  // npad: (run, sigma octave, row key, row) sorted
+    unsigned long long* rowkeys;  // npad: (run, sigma half-octave, row key, row) sorted
     double* scols;             // n_total x 9 sorted columns (u_k, q_k)
     double* skey;              // n_total sorted sort-coordinate values
     double* rwin;              // n_total per-row window half-widths (slot off_r + j)

@@ -429,14 +429,14 @@ __global__ __launch_bounds__(kBlock) void bcompact_scatter_kernel(BatchArgs a)
 
 // Weight window, per run (as the single-run pass): the sort coordinate d* of
 // largest column variance; columns sorted by (run, u_{k,d*}); rows sorted by
-// (run, sigma octave descending, u_{j,d*}); each row's half-width comes from its parent's
+// (run, sigma half-octave descending, u_{j,d*}); each row's half-width comes from its parent's
 // term (wterm::window_halfwidth) and each 128-row block gets the union of its
 // rows' column ranges.  One batch-wide bitonic
 // sort per key set: the run index in the top 12 bits keeps every run's keys in
 // its own slot range [off_r, off_r + N_r).
 using wterm::coord_key32;
 using wterm::lower_index;
-using wterm::sigma_octave;
+using wterm::sigma_half_octave;
 using wterm::wave_max;
 using wterm::wave_min;
 
@@ -505,9 +505,9 @@ __global__ __launch_bounds__(kBlock) void bkeys_kernel(BatchArgs a)
                        ? run | (coord_key32(R.cols[k * 9 + ds]) << 20) | k
                        : run | (0xFFFFFFFFull << 20) | k;
     const int nx = S.nxt;
-    // octaves in descending order: the widest windows are dispatched first
-    const unsigned long long oct = 63ull - sigma_octave(R.sigma[nx][k]);
-    a.rowkeys[i] = run | (oct << 46) | ((coord_key32(R.u[nx][k * kNP + ds]) >> 6) << 20) | k;
+    // half-octaves in descending order: the widest windows are dispatched first
+    const unsigned long long oct = 127ull - sigma_half_octave(R.sigma[nx][k]);
+    a.rowkeys[i] = run | (oct << 45) | ((coord_key32(R.u[nx][k * kNP + ds]) >> 7) << 20) | k;
     const double* uj = R.u[nx] + k * kNP;
     const int32_t par = R.parent[nx][k];
     const bool ok = par >= 0 && par < R.N;

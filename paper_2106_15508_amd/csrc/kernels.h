@@ -128,7 +128,7 @@ struct WeightArgs {
     double* partial;        // chunks x N row sums per column chunk
     double* logw;           // N
     // windowed evaluation: columns sorted by one coordinate, rows by
-    // (step-size octave, same coordinate); each workgroup visits only the
+    // (step-size half-octave, same coordinate); each workgroup visits only the
     // columns that can give a nonzero term
     unsigned long long* rowkeys;  // Npad sort keys (row index in the low 32 bits)
     unsigned long long* colkeys;  // Npad sort keys (column index in the low 32 bits)

@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void resample_write_kernel(ResampleArgs a)
 using wterm::kTile;
 using wterm::coord_key32;
 using wterm::lower_index;
-using wterm::sigma_octave;
+using wterm::sigma_half_octave;
 using wterm::wave_max;
 using wterm::wave_min;
 
@@ -247,7 +247,7 @@ using wterm::wave_min;
 // where every omitted exponential is below e^-710).  Per stage: pick the
 // coordinate d* with the largest spread among the columns (the windows then
 // exclude the most columns: sigma is the same in every coordinate), sort the
-// columns by it, sort the rows by (octave of sigma, descending; u_d*), and let every
+// columns by it, sort the rows by (half-octave of sigma, descending; u_d*), and let every
 // workgroup (128 consecutive sorted rows) visit only the union of its rows'
 // windows; a wave also skips tiles outside its own lanes' union.
 
@@ -329,9 +329,9 @@ __global__ __launch_bounds__(kBlock) void wrowkeys_kernel(WeightArgs a)
         return;
     }
     const int ds = *a.dstar;
-    // octaves in descending order: the widest windows are dispatched first
+    // half-octaves in descending order: the widest windows are dispatched first
     const unsigned long long hi =
-        ((63ull - sigma_octave(a.sigma[i])) << 26) | (coord_key32(a.u[i * kNP + ds]) >> 6);
+        ((127ull - sigma_half_octave(a.sigma[i])) << 25) | (coord_key32(a.u[i * kNP + ds]) >> 7);
     a.rowkeys[i] = (hi << 32) | (unsigned long long)i;
     double uj[kNP];
 #pragma unroll

@@ -197,6 +197,8 @@ struct TrajArgs {
 };
 
 void launch_propose(const ProposeArgs& a, bool round0, hipStream_t s);
+// Proposal lanes the current device holds at once (one round of resident waves).
+int64_t propose_resident_lanes();
 void launch_compact(const CompactArgs& a, hipStream_t s);
 void launch_resample(const ResampleArgs& a, hipStream_t s);
 // The weight pass in three parts, so that the caller can time the sum kernel

@@ -181,6 +181,14 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBloc
 
 }  // namespace
 
+int64_t propose_resident_lanes()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return (int64_t)cus * 4 * ABCSMC_PROPOSE_WAVES * kWave;  // 4 SIMDs per compute unit
+}
+
 void launch_propose(const ProposeArgs& a, bool round0, hipStream_t s)
 {
     const dim3 g(grid_for(a.count)), b(kBlock);

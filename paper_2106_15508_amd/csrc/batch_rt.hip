@@ -255,7 +255,11 @@ int initial_states(abcsmc_batch* b)
     b->hst.assign(b->R, BState{});
     for (auto& st : b->hst) {
         st.eps = st.eps1 = st.eps_next = INFINITY;
-        st.rate = 0.5;
+        // acceptance-rate guess for stage 1 (no rate measured yet): its first
+        // perturbations accept 0.8-0.9 of the proposals on the uneven batch;
+        // 0.8 issued 2% fewer simulations and ran 1% faster than 0.5 (the
+        // persistent kernel tops up a run that falls short)
+        st.rate = 0.8;
     }
     BCHK(b, hipMemcpyAsync(b->ws + b->off_st, b->hst.data(), b->hst.size() * sizeof(BState), hipMemcpyHostToDevice,
                            b->stream));

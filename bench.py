@@ -36,7 +36,7 @@ PEAK_HBM_GBS = 8000.0
 
 # FP64 flops of one importance-weight term as the kernel evaluates it (every
 # FP64 instruction counted, fma = 2): 8 differences, 8 fma for the squared
-# distance, exponent scaling 1, table exp 11 (round 1, reduced argument 1,
+# distance, exponent scaling 1, table exp 11 (rounding to an integer 1, reduced argument 1,
 # integer conversion 1, 3 fma 6, table product 1, 2^k 1), weight times term
 # fused into the running sum 2.
 FLOPS_PER_PAIR = 8 + 16 + 1 + 11 + 2

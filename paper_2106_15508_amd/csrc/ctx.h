@@ -103,7 +103,7 @@ struct abcsmc_ctx {
     char* stage_host = nullptr;  // pinned staging for the copy-out calls (allocated on first use)
     size_t stage_bytes = 0;
     double last_rate = 0.5;      // acceptance rate of the last stage (batch sizing)
-    int64_t resident = 0;        // proposal lanes resident on the device at once
+    int64_t first_batch = 0;     // largest first batch of stage 1 (no measured rate yet)
     double mcmc_s = 0.0;         // MCMC variant: current step size
     int32_t mcmc_tunes = 0;      // MCMC variant: tuned batches so far
     int64_t mcmc_nacc = 0;       // MCMC variant: acceptances of the tuned batches

@@ -197,8 +197,10 @@ struct TrajArgs {
 };
 
 void launch_propose(const ProposeArgs& a, bool round0, hipStream_t s);
-// Proposal lanes the current device holds at once (one round of resident waves).
-int64_t propose_resident_lanes();
+// Largest first batch of a stage without a measured acceptance rate: 768
+// proposals per compute unit of the current device (three 64-lane waves per
+// SIMD, a round and a half of the proposal kernel's resident waves).
+int64_t propose_first_batch_lanes();
 void launch_compact(const CompactArgs& a, hipStream_t s);
 void launch_resample(const ResampleArgs& a, hipStream_t s);
 // The weight pass in three parts, so that the caller can time the sum kernel

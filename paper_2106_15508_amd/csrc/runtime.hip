@@ -275,7 +275,7 @@ int abcsmc_init(const abcsmc_config* cfg, const int64_t* obs, abcsmc_ctx** out)
         x->own_ws = true;
     }
     bind_pops(x);
-    x->resident = propose_resident_lanes();
+    x->first_batch = propose_first_batch_lanes();
     for (auto& ev : x->ev)
         if (hipEventCreate(&ev) != hipSuccess) {
             x->err = "hipEventCreate failed";
@@ -435,9 +435,9 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
             B = (int64_t)std::ceil(need / rate * 1.1) + 2048;
             B = (B + kBlock - 1) / kBlock * kBlock;
             // stage 1 has no measured acceptance rate yet: its first batch is
-            // at most one round of resident waves (a partly filled extra round
-            // takes as long as a full one); later batches use the rate measured
-            if (r == 1 && base == 0 && x->resident > 0 && B > x->resident) B = x->resident;
+            // capped (a batch sized by the 0.5 guess simulated twice the
+            // proposals needed at C2); later batches use the rate measured
+            if (r == 1 && base == 0 && x->first_batch > 0 && B > x->first_batch) B = x->first_batch;
             if (B > cap) B = cap;
         }
         if (base + B > c.max_proposals) B = c.max_proposals - base;

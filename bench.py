@@ -52,8 +52,8 @@ TRAFFIC_SOURCES = ("paper_2106_15508_amd/csrc/smc.hip", "paper_2106_15508_amd/cs
                    "paper_2106_15508_amd/build.py")
 TRAFFIC_MEASURED = {
     # c2, per launch: FETCH_SIZE KiB x 2 + WRITE_SIZE KiB x 1
-    ("c112b97c5db801f3", "c2", "weights_kernel"): 559957 * 1024 * 2 + 26916 * 1024,
-    ("c112b97c5db801f3", "c2", "propose_kernel"): 15981 * 1024 * 2 + 15874 * 1024,
+    ("e6370fa24c3b5b22", "c2", "weights_kernel"): 559541 * 1024 * 2 + 26916 * 1024,
+    ("e6370fa24c3b5b22", "c2", "propose_kernel"): 15984 * 1024 * 2 + 15874 * 1024,
 }
 # FP64 flops of one simulated proposal-day with all five transitions in the
 # normal branch of the binomial draw: state sums 2, g (log 34, exp 33, 4) 71,

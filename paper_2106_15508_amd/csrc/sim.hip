@@ -13,10 +13,10 @@ namespace {
 // Proposal kernel of one batch: lane p makes proposal j = base + p and
 // publishes the wave's acceptance ballot for the ordered compaction.
 // ---------------------------------------------------------------------------
-// Waves per SIMD the register allocation aims for.  The day loop is a chain
-// of long-latency FP64 divides, square roots and series; two waves per SIMD
-// with the registers that allows ran the kernel 1.8% faster than three (with
-// a few registers spilled to lanes) and 6% faster than four.
+// Waves per SIMD the register allocation aims for.  The kernel needs 156
+// VGPRs, so three waves per SIMD are resident whether two or three are asked
+// for; asking for two gave a slightly different instruction schedule that ran
+// 1.8% faster, and asking for four (128 VGPRs) was 6% slower.
 #ifndef ABCSMC_PROPOSE_WAVES
 #define ABCSMC_PROPOSE_WAVES 2
 #endif

@@ -918,6 +918,19 @@ void ref_words(uint64_t seed, uint32_t index, uint32_t round, uint32_t purpose, 
     for (uint32_t w = 0; w < nwords; ++w) out[w] = ref_word(seed, index, round, purpose, sub, w);
 }
 
+/* Number of the n simulations of u on streams index0 .. index0+n-1 of
+ * `round` whose distance is at most eps (acceptance of §II-C). */
+int64_t ref_accept_count(const ref_config* cfg, const int64_t* obs, const double u[REF_NPAR], double eps,
+                         uint32_t round, uint32_t index0, int64_t n)
+{
+    int64_t* traj = (int64_t*)malloc((size_t)(cfg->n_days + 1) * 6 * sizeof(int64_t));
+    int64_t acc = 0;
+    for (int64_t i = 0; i < n; ++i)
+        acc += ref_sim_distance(cfg, obs, u, round, index0 + (uint32_t)i, traj) <= eps;
+    free(traj);
+    return acc;
+}
+
 void ref_binomial_many(const int64_t* n, const double* p, const uint64_t* w, int64_t* out, int64_t cnt)
 {
     for (int64_t i = 0; i < cnt; ++i) out[i] = ref_binomial(n[i], p[i], w[i]);

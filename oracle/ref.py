@@ -91,6 +91,7 @@ def lib():
             "ref_beta_general_many": (None, [d, d, u64, u32, u32, u32, vp, i64]),
             "ref_gamma_many": (None, [d, u64, u32, u32, u32, vp, i64]),
             "ref_beta_shape_real": (None, [vp, i32, d, d, vp, vp]),
+            "ref_accept_count": (i64, [vp, vp, vp, d, u32, u32, i64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -248,6 +249,15 @@ def sim_distance(w, obs, u, rnd: int, index: int, **over) -> float:
     u = np.ascontiguousarray(u, dtype=np.float64)
     traj = np.zeros((cfg.n_days + 1, 6), dtype=np.int64)
     return lib().ref_sim_distance(C.byref(cfg), _p(obs), _p(u), rnd, index, _p(traj))
+
+
+def accept_count(w, obs, u, eps: float, rnd: int, index0: int, n: int, **over) -> int:
+    """How many of n simulations of u (streams index0.. of stage rnd) have
+    distance <= eps."""
+    cfg = make_config(w, **over)
+    obs = np.ascontiguousarray(obs, dtype=np.int64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    return lib().ref_accept_count(C.byref(cfg), _p(obs), _p(u), eps, rnd, index0, n)
 
 
 def beta_general(a: float, b: float, seed: int, index0: int, rnd: int, sub: int, n: int) -> np.ndarray:

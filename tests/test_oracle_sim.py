@@ -157,14 +157,99 @@ def test_one_day_conditional_means(oracle):
     assert abs(n5.mean() - mean5) < 5 * math.sqrt(mean5 / cnt) + 0.5
 
 
-def test_normal_floor_sampler_properties(oracle):
-    """The paper's own transition sampler (floor of a normal with mean h):
-    conservation, non-negativity, and one-day mean S->I count near h."""
+def test_normal_floor_trajectory_properties(oracle):
+    """The paper's own transition sampler in the simulator: conservation,
+    no negative count, R never decreasing."""
     w = W.C2.with_(n_days=30, sampler=W.SAMPLER_NORMAL_FLOOR)
     for i in range(20):
         tr = oracle.simulate(w, W.THETA_TRUE, 8, 1, i, obs0=(1000, 0, 0))
         assert np.all(tr.sum(1) == w.population) and np.all(tr >= 0)
         assert np.all(np.diff(tr[:, 3]) >= 0)
+
+
+def _floor_normal_draws(oracle, n, h, cnt, index):
+    """cnt floor-normal draws for (n, h), one Philox word each (stream of
+    particle `index`, a purpose no run uses)."""
+    ws = oracle.words(77, index, 5, 9, 0, cnt)
+    return np.array([oracle.lib().ref_normal_floor(n, h, int(x)) for x in ws], dtype=np.int64)
+
+
+@pytest.mark.parametrize("h", [12.5, 1e3, 1e6])
+def test_normal_floor_moments(oracle, h):
+    """Section II-B draws a transition count as the floor of a normal with
+    mean h and spread sqrt(h), read as the standard deviation (reading R3:
+    the Poisson(h) it stands in for has variance h).  With the source
+    count far above h the floor of N(h, h) has mean h - 1/2 and variance
+    h + 1/12 (a uniform rounding error independent of the normal, Sheppard).
+    Reading sqrt(h) as the variance instead gives variance sqrt(h); rounding
+    instead of flooring moves the mean by 1/2 (28 standard errors at h = 12.5)."""
+    cnt = 40000
+    x = _floor_normal_draws(oracle, 10**12, h, cnt, int(h) % 1000).astype(np.float64)
+    se = math.sqrt((h + 1.0 / 12.0) / cnt)
+    assert abs(x.mean() - (h - 0.5)) < 5 * se, (x.mean(), h - 0.5, se)
+    var = x.var(ddof=1)
+    assert abs(var / (h + 1.0 / 12.0) - 1.0) < 0.05, (var, h)
+
+
+@pytest.mark.parametrize("h", [3.0, 12.5])
+def test_normal_floor_exact_law(oracle, h):
+    """The clamped law is P(X = 0) = Phi((1 - h)/sqrt h), P(X = k) =
+    Phi((k + 1 - h)/sqrt h) - Phi((k - h)/sqrt h) for 0 < k: chi-square
+    of 60000 draws against it."""
+    cnt = 60000
+    x = _floor_normal_draws(oracle, 10**9, h, cnt, 500 + int(h))
+    assert x.min() >= 0
+    sd = math.sqrt(h)
+    kmax = int(h + 7 * sd) + 1
+    edges = np.arange(0, kmax + 1, dtype=np.float64)
+    cdf = stats.norm.cdf((edges + 1.0 - h) / sd)
+    p = np.diff(np.concatenate([[0.0], cdf]))
+    p[-1] += 1.0 - cdf[-1]
+    obs = np.bincount(np.minimum(x, kmax), minlength=kmax + 1).astype(np.float64)
+    big = p * cnt >= 5
+    obs_k = np.append(obs[big], obs[~big].sum())
+    exp_k = np.append(p[big], p[~big].sum()) * cnt
+    assert stats.chisquare(obs_k, exp_k).pvalue > 1e-4
+
+
+def test_normal_floor_clamps(oracle):
+    """Clamped to [0, n]: at h = 0.5 three quarters of the draws are 0
+    (Phi(1/sqrt 2) = 0.760); with n = h = 100 half of them are n; h <= 0 or
+    n <= 0 gives 0."""
+    cnt = 20000
+    x = _floor_normal_draws(oracle, 10**6, 0.5, cnt, 1)
+    assert x.min() == 0
+    p0 = stats.norm.cdf(0.5 / math.sqrt(0.5))
+    assert abs((x == 0).mean() - p0) < 5 * math.sqrt(p0 * (1 - p0) / cnt)
+    y = _floor_normal_draws(oracle, 100, 100.0, cnt, 2)
+    assert y.max() == 100 and y.min() >= 0
+    assert abs((y == 100).mean() - 0.5) < 5 * math.sqrt(0.25 / cnt)
+    for n, h in ((0, 5.0), (-3, 5.0), (10, 0.0), (10, -1.0)):
+        assert oracle.lib().ref_normal_floor(n, h, 12345) == 0
+
+
+def test_normal_floor_one_day_counts(oracle):
+    """In the simulator every transition of a day is floor(N(h, sqrt h))
+    with the eq. 5 hazard h of the start-of-day state: at P = 1e7 with 50000
+    active cases the S->I, A->R and A->D counts have means h - 1/2 and
+    variances h + 1/12, and counts drawn from different words are
+    uncorrelated."""
+    P, A0 = 10_000_000, 50_000
+    w = W.C2.with_(n_days=1, sampler=W.SAMPLER_NORMAL_FLOOR)
+    th = (0.3, 2.0, 0.5, 0.05, 0.1, 0.005, 0.2, 1.0)
+    cnt = 4000
+    tr = np.stack([oracle.simulate(w, th, 6, 1, i, obs0=(A0, 0, 0)) for i in range(cnt)]).astype(np.float64)
+    S0, I0 = float(P - 2 * A0), float(A0)
+    g = th[0] + th[1] / (1 + A0 ** th[2])
+    n1 = S0 - tr[:, 1, 0]
+    n3, n4 = tr[:, 1, 3], tr[:, 1, 4]
+    for x, h in ((n1, g * I0 / P * S0), (n3, th[3] * A0), (n4, th[5] * A0)):
+        se = math.sqrt((h + 1.0 / 12.0) / cnt)
+        assert abs(x.mean() - (h - 0.5)) < 5 * se, (x.mean(), h)
+        assert abs(x.var(ddof=1) / (h + 1.0 / 12.0) - 1.0) < 0.1
+    lim = 4.0 / math.sqrt(cnt)
+    assert abs(np.corrcoef(n1, n3)[0, 1]) < lim
+    assert abs(np.corrcoef(n3, n4)[0, 1]) < lim
 
 
 def test_paired_normal_draws_are_uncorrelated(oracle):

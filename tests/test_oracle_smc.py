@@ -213,3 +213,164 @@ def test_replaying_own_schedule_is_identity(oracle):
     c = oracle.run(wl.with_(eps_schedule=(a.eps_next[0], 0.8 * a.eps_next[1])), obs)
     assert np.array_equal(a.u[:2], c.u[:2]) and c.eps[2] == 0.8 * a.eps_next[1]
     assert np.all(c.dist[2] <= c.eps[2]) and not np.array_equal(a.u[2], c.u[2])
+
+
+# ----------------------------------------------------- perturbation law (eq. 17)
+
+def _perturb_many(oracle, w, rnd, u_prev, q, beta_a, beta_b, cnt, **over):
+    """cnt proposals (indices 0..cnt-1) of stage rnd from the oracle's
+    perturbation: arrays of attempts, u, sigma, parent."""
+    Cc = np.cumsum(np.asarray(q, dtype=np.uint64)).astype(np.uint64)
+    out = [oracle.perturb(w, rnd, j, u_prev, Cc, beta_a, beta_b, **over) for j in range(cnt)]
+    a = np.array([o[0] for o in out])
+    u = np.array([o[1] for o in out])
+    s = np.array([o[2] for o in out])
+    par = np.array([o[3] for o in out])
+    return a, u, s, par
+
+
+@pytest.mark.parametrize("variance", [False, True])
+def test_perturbation_offsets_are_iid_standard_normal(oracle, variance):
+    """Eq. 17 in the unit cube: u = u_parent + sigma z with z ~ N(0, I_8).
+    With a fixed step size (the MCMC variant's s) and every parent at least
+    40 sigma inside the cube no proposal is redrawn, so the eight
+    standardised offsets (u - u_parent)/sigma must each be N(0, 1) (KS) and
+    pairwise uncorrelated (|r| < 4/sqrt(n)); sigma is s, or sqrt(s) when s
+    is read as a variance (eq. 12).  A deviate reused across two
+    coordinates, sigma^2 in place of sigma, or a wrong scale fails this."""
+    rng = np.random.default_rng(11)
+    M, cnt, sig = 16, 20000, 0.01
+    u_prev = rng.uniform(0.4, 0.6, size=(M, 8))
+    q = rng.integers(1, 1000, M)
+    s = sig * sig if variance else sig
+    w = W.tiny(step_schedule=W.STEP_MCMC, step_is_variance=variance)
+    a, u, sg, par = _perturb_many(oracle, w, 3, u_prev, q, s, 0, cnt)
+    assert np.all(a == 1)
+    assert np.all(sg == (math.sqrt(s) if variance else s))
+    z = (u - u_prev[par]) / sig
+    for d in range(8):
+        assert stats.kstest(z[:, d], "norm").pvalue > 1e-4, d
+    r = np.corrcoef(z.T)
+    lim = 4.0 / math.sqrt(cnt)
+    assert np.all(np.abs(r[np.triu_indices(8, 1)]) < lim)
+    # the parents follow the categorical law of eq. 11
+    obs = np.bincount(par, minlength=M)
+    assert stats.chisquare(obs, q / q.sum() * cnt).pvalue > 1e-4
+
+
+def test_perturbation_redraws_the_whole_triple(oracle):
+    """A proposal outside [0,1]^8 is redrawn with a new parent, step size
+    and normal vector (reading R10), so each attempt lands inside with
+    probability p = sum_k P_k Pr(inside | k): the attempt count is
+    geometric(p), and the accepted parent is k with probability
+    P_k Pr(inside | k) / p.  Two parents with q = (1, 3): one deep inside,
+    one with its first coordinate sigma/2 from the face u = 0 (inside with
+    probability Phi(1/2)).  Keeping the parent and redrawing only z would
+    give the second parent probability 3/4 instead of 0.675; its accepted
+    offsets are N(0, 1) truncated below at -1/2."""
+    sig, cnt = 0.05, 20000
+    u_prev = np.full((2, 8), 0.5)
+    u_prev[1, 0] = 0.5 * sig
+    q = np.array([1, 3])
+    w = W.tiny(step_schedule=W.STEP_MCMC)
+    a, u, sg, par = _perturb_many(oracle, w, 2, u_prev, q, sig, 0, cnt)
+    assert np.all(a >= 1) and np.all((u >= 0) & (u <= 1))
+    pin = stats.norm.cdf(0.5)
+    p = 0.25 + 0.75 * pin
+    pb = 0.75 * pin / p
+    nb = int((par == 1).sum())
+    assert abs(nb / cnt - pb) < 5 * math.sqrt(pb * (1 - pb) / cnt), (nb / cnt, pb)
+    kmax = 6
+    obs = np.array([(a == k).sum() for k in range(1, kmax)] + [(a >= kmax).sum()], dtype=np.float64)
+    exp = np.array([(1 - p) ** (k - 1) * p for k in range(1, kmax)] + [(1 - p) ** (kmax - 1)]) * cnt
+    assert stats.chisquare(obs, exp).pvalue > 1e-4
+    z0 = (u[par == 1, 0] - u_prev[1, 0]) / sig
+    assert stats.kstest(z0, stats.truncnorm(-0.5, np.inf).cdf).pvalue > 1e-4
+
+
+def test_perturbation_step_size_redrawn_with_the_triple(oracle):
+    """With the eq. 16 law s ~ Beta(1, 2) and one parent at the centre of
+    the cube, an attempt lands inside with probability
+    g(s) = (2 Phi(1/(2 s)) - 1)^8, so the accepted step sizes have density
+    proportional to f(s) g(s) (f the Beta(1, 2) density) and the attempts
+    are geometric with p = integral of f g.  Keeping s across the redraws
+    would leave the accepted step sizes close to f itself."""
+    from scipy import integrate
+    cnt = 20000
+    u_prev = np.full((1, 8), 0.5)
+    w = W.tiny()
+    a, u, sg, par = _perturb_many(oracle, w, 1, u_prev, [1], 1.0, 2, cnt)
+    assert np.all(a > 0) and np.all(par == 0)
+
+    def f(s):
+        return 2.0 * (1.0 - s)
+
+    def g(s):
+        return (2.0 * stats.norm.cdf(0.5 / s) - 1.0) ** 8
+
+    p = integrate.quad(lambda s: f(s) * g(s), 0, 1, epsabs=1e-13)[0]
+    grid = np.linspace(0.0, 1.0, 4001)
+    dens = np.array([f(s) * g(s) if s > 0 else 2.0 for s in grid])
+    cdf = np.concatenate([[0.0], np.cumsum((dens[1:] + dens[:-1]) * 0.5 * np.diff(grid))])
+    cdf /= cdf[-1]
+    assert stats.kstest(sg, lambda x: np.interp(x, grid, cdf)).pvalue > 1e-4
+    kmax = 8
+    obs = np.array([(a == k).sum() for k in range(1, kmax)] + [(a >= kmax).sum()], dtype=np.float64)
+    exp = np.array([(1 - p) ** (k - 1) * p for k in range(1, kmax)] + [(1 - p) ** (kmax - 1)]) * cnt
+    assert stats.chisquare(obs, exp).pvalue > 1e-4
+
+
+# ------------------------------------------------- full SMC against a grid posterior
+
+def test_weighted_population_is_the_abc_posterior(oracle):
+    """The importance weights (reading R17) make each stage's population a
+    sample of the ABC posterior pi(theta) Pr(d <= eps_i | theta) (§II-C,
+    §II-D).  Toy: every prior interval but beta's is a single point
+    (lo = hi = the generating value), P = 60, 6 days, so the posterior of
+    the one free parameter is known on a grid from the acceptance
+    probability, estimated by 3000 simulations per grid point on streams no
+    run uses.  Twelve runs (seeds 1..12, N = 1000, eq. 16 step sizes, the
+    same replayed tolerances) give W-weighted means and standard deviations
+    that must agree with the grid posterior's within 4 standard errors of
+    the seed-to-seed spread, at stages 1, 2 and 3.  The unweighted
+    population is biased (more than 30 standard errors at every stage), so
+    the agreement is the weights' doing."""
+    th = list(W.THETA_TRUE)
+    free = 3
+    lo, hi = list(th), list(th)
+    lo[free], hi[free] = 0.0, 0.5
+    w = W.Workload("toy", population=60, n_days=6, n_particles=1000, n_rounds=4, lo=tuple(lo), hi=tuple(hi),
+                   obs_seed=4242, seed=1)
+    obs = oracle.observations(w)
+    sched = tuple(oracle.run(w, obs).eps_next[:3])
+    M, S, U = [], [], []
+    for seed in range(1, 13):
+        r = oracle.run(w.with_(seed=seed, eps_schedule=sched), obs)
+        assert r.rc == 0 and np.array_equal(r.eps[1:], sched)
+        x = r.theta(w)[:, :, free]
+        m = [float((r.W[i] * x[i]).sum()) for i in (1, 2, 3)]
+        # weighted standard deviation with the 1 / (1 - sum W^2) bias correction
+        s = [math.sqrt(float((r.W[i] * (x[i] - m[i - 1]) ** 2).sum()) / (1.0 - float((r.W[i] ** 2).sum())))
+             for i in (1, 2, 3)]
+        M.append(m)
+        S.append(s)
+        U.append([float(x[i].mean()) for i in (1, 2, 3)])
+    M, S, U = np.array(M), np.array(S), np.array(U)
+    G, n = 80, 3000
+    grid_u = (np.arange(G) + 0.5) / G
+    grid_th = lo[free] + grid_u * (hi[free] - lo[free])
+    for i in (1, 2, 3):
+        p = np.zeros(G)
+        for g in range(G):
+            u = np.full(8, 0.5)
+            u[free] = grid_u[g]
+            p[g] = oracle.accept_count(w, obs, u, sched[i - 1], 0xABC, g * n, n) / n
+        gm = float((p * grid_th).sum() / p.sum())
+        gs = math.sqrt(float((p * (grid_th - gm) ** 2).sum() / p.sum()))
+        k = i - 1
+        se_m = M[:, k].std(ddof=1) / math.sqrt(len(M))
+        se_s = S[:, k].std(ddof=1) / math.sqrt(len(S))
+        se_u = U[:, k].std(ddof=1) / math.sqrt(len(U))
+        assert abs(M[:, k].mean() - gm) < 4 * se_m + 1e-3 * gs, (i, M[:, k].mean(), gm, se_m)
+        assert abs(S[:, k].mean() - gs) < 4 * se_s + 1e-3 * gs, (i, S[:, k].mean(), gs, se_s)
+        assert abs(U[:, k].mean() - gm) > 30 * se_u, (i, U[:, k].mean(), gm, se_u)

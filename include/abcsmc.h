@@ -367,6 +367,19 @@ int64_t abcsmc_mlp_param_count(void); /* 134659 */
 int abcsmc_mlp_init(uint64_t seed, float* params);
 /* out n x 3 = network(x n x 8); 1 <= n <= 65536. */
 int abcsmc_mlp_forward(const float* params, int64_t n, const float* x, float* out);
+/* Allocation-free variant of abcsmc_mlp_forward, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  params (abcsmc_mlp_param_count()
+ * floats), x (n x 8) and out (n x 3) are DEVICE pointers owned by the
+ * caller; 1 <= n <= 65536, else ABCSMC_EINVAL.  The work is enqueued on
+ * `stream` (a hipStream_t of the current device; NULL = the null stream) and
+ * the call returns without waiting.  The bfloat16 copy of the network that
+ * the kernels read is kept in a fixed device array of the library (269,568
+ * bytes, one per GPU, held until the process ends; its address is looked up
+ * once per device), so the call allocates nothing.  Every call on one GPU
+ * shares that array: calls that overlap on one GPU race (order them on one
+ * stream).  Results are bit-identical to abcsmc_mlp_forward's. */
+int abcsmc_mlp_forward_noalloc(const float* params, int64_t n, const float* x, float* out, void* stream);
 /* Gradient of the loss mean over n x 3 of (out - y)^2 with respect to the
  * parameters (same layout), and the loss; 1 <= n <= 16384. */
 int abcsmc_mlp_gradients(const float* params, int64_t n, const float* x, const float* y, float* grad,

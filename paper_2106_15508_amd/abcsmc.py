@@ -38,7 +38,7 @@ EXPORTS = (
     "abcsmc_batch_free", "abcsmc_batch_last_error",
     "abcsmc_surrogate_enable", "abcsmc_surrogate_disable", "abcsmc_surrogate_info_get", "abcsmc_surrogate_params",
     "abcsmc_surrogate_data", "abcsmc_surrogate_audit", "abcsmc_mlp_param_count", "abcsmc_mlp_init",
-    "abcsmc_mlp_forward", "abcsmc_mlp_gradients", "abcsmc_mlp_train", "abcsmc_predict",
+    "abcsmc_mlp_forward", "abcsmc_mlp_forward_noalloc", "abcsmc_mlp_gradients", "abcsmc_mlp_train", "abcsmc_predict",
 )
 
 
@@ -165,6 +165,7 @@ def load(path: Optional[str] = None):
         "abcsmc_mlp_param_count": (i64, []),
         "abcsmc_mlp_init": (C.c_int, [u64, vp]),
         "abcsmc_mlp_forward": (C.c_int, [vp, i64, vp, vp]),
+        "abcsmc_mlp_forward_noalloc": (C.c_int, [vp, i64, vp, vp, vp]),
         "abcsmc_mlp_gradients": (C.c_int, [vp, i64, vp, vp, vp, vp]),
         "abcsmc_mlp_train": (C.c_int, [vp, i64, vp, vp, i32, i32, d, vp]),
         "abcsmc_predict": (C.c_int, [vp, i32, u64, i32, vp, vp]),
@@ -407,6 +408,13 @@ def mlp_forward(params, x) -> np.ndarray:
     out = np.zeros((n, 3), np.float32)
     _check(load().abcsmc_mlp_forward(_p(params), n, _p(x), _p(out)))
     return out
+
+
+def mlp_forward_noalloc(params_ptr: int, n: int, x_ptr: int, out_ptr: int, stream: int = 0) -> None:
+    """abcsmc_mlp_forward_noalloc on caller device memory (raw device
+    addresses, e.g. torch tensors' data_ptr()); enqueued on `stream`."""
+    _check(load().abcsmc_mlp_forward_noalloc(C.c_void_p(params_ptr), n, C.c_void_p(x_ptr), C.c_void_p(out_ptr),
+                                             C.c_void_p(stream or None)))
 
 
 def mlp_gradients(params, x, y):

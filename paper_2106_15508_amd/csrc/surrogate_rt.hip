@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -443,6 +444,39 @@ int hook_fail(hipError_t e)
         if (e_ != hipSuccess) return hook_fail(e_); \
     } while (0)
 
+// ---------------------------------------------------------------------------
+// Allocation-free network forward.  The bfloat16 copy of the network that the
+// fused scoring kernel reads lives in `scratch`, a file-scope device array
+// (each GPU the library runs on holds its own copy until the process ends),
+// instead of memory allocated per call.  In host code `scratch` only names
+// the symbol: its device address on the current GPU is looked up once per
+// device with hipGetSymbolAddress and cached; kernels receive that address.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchElems = ((size_t)kMlpParams + 127) / 128 * 128;  // 269,568 bytes
+static __device__ __align__(256) __bf16 scratch[kScratchElems];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+hipError_t scratch_address(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -608,6 +642,17 @@ int abcsmc_mlp_forward(const float* params, int64_t n, const float* xs, float* o
         HOOKCHK(hipGetLastError());
         HOOKCHK(hipMemcpy(out, O, (size_t)n * kOut * sizeof(float), hipMemcpyDeviceToHost));
     }
+    return ABCSMC_OK;
+}
+
+int abcsmc_mlp_forward_noalloc(const float* params, int64_t n, const float* x, float* out, void* stream)
+{
+    if (!params || !x || !out) return fail(nullptr, ABCSMC_EINVAL, "NULL argument");
+    if (n < 1 || n > kInferRows) return fail(nullptr, ABCSMC_EINVAL, "n must be in [1, 65536]");
+    void* wb = nullptr;
+    HOOKCHK(scratch_address(&wb));
+    mlp_infer(params, (__bf16*)wb, x, n, out, nullptr, (hipStream_t)stream);
+    HOOKCHK(hipGetLastError());
     return ABCSMC_OK;
 }
 

@@ -1,6 +1,9 @@
-"""Batched mode: every run of a batch gives the same bits as the same run
-alone (single-run context, itself bit-exact against the oracle), under any
-schedule, with graph replays checked stage by stage against eager runs."""
+"""Batched mode: every run of a batch is checked stage by stage against the
+oracle's own run (eqs. 8-11, 16-17: indices, u, d, sigma, parent, attempts
+and tolerances bit for bit, weights within 1e-12), under both flag settings
+and two launch schedules; and it gives the same bits as the same run alone
+(single-run context) under any schedule, with graph replays checked stage by
+stage against eager runs."""
 import numpy as np
 import pytest
 
@@ -51,6 +54,54 @@ def _same(b, p, bi, pi_):
     assert _bits([bi["eps_next"]])[0] == _bits([pi_["eps_next"]])[0]
     assert bi["proposals"] == pi_["proposals"]
     np.testing.assert_allclose(b["W"], p["W"], rtol=1e-12, atol=0)
+
+
+W_RTOL = 1e-12
+
+
+def _same_as_oracle(p, info, ref, i, tag):
+    """Stage i of a batched run against stage i of the oracle's run."""
+    assert info["eps"] == ref.eps[i] or (np.isinf(info["eps"]) and np.isinf(ref.eps[i])), tag
+    assert _bits([info["eps_next"]])[0] == _bits([ref.eps_next[i]])[0], tag
+    assert info["proposals"] == ref.proposals[i], tag
+    assert np.array_equal(p["index"], ref.index[i]), tag
+    assert np.array_equal(_bits(p["u"]), _bits(ref.u[i])), tag
+    assert np.array_equal(_bits(p["d"]), _bits(ref.dist[i])), tag
+    assert np.array_equal(_bits(p["sigma"]), _bits(ref.sigma[i])), tag
+    assert np.array_equal(p["parent"], ref.parent[i]), tag
+    assert np.array_equal(p["attempts"], ref.attempts[i]), tag
+    if i > 0:
+        assert info["beta_a"] == ref.beta_a[i] and info["beta_b"] == ref.beta_b[i], tag
+        np.testing.assert_allclose(p["W"], ref.W[i], rtol=W_RTOL, atol=0, err_msg=str(tag))
+        np.testing.assert_allclose(p["logw"], ref.logw[i], rtol=0, atol=1e-12, err_msg=str(tag))
+    else:
+        assert np.all(p["W"] == 1.0 / len(p["W"])), tag
+
+
+@pytest.fixture(scope="module")
+def oracle_runs(oracle):
+    runs = _runs()
+    obs = [oracle.observations(w) for w in runs]
+    refs = [oracle.run(w, o, n_rounds=4) for w, o in zip(runs, obs)]
+    assert all(r.rc == 0 for r in refs)
+    return runs, obs, refs
+
+
+@pytest.mark.parametrize("flags", [0, A.F_EARLY_EXIT])
+@pytest.mark.parametrize("sched", [{}, dict(propose_blocks=64, run_order=2, weight_cols=2048, issue_margin=1.5)])
+def test_batched_equals_oracle(oracle_runs, flags, sched):
+    """Six uneven runs (N 256..4096, both samplers, fixed and eq. 16 step
+    laws, s read as a variance) in one batch, four stages each, against the
+    oracle's runs."""
+    runs, obs, refs = oracle_runs
+    with A.Batch(runs, obs, flags=flags) as b:
+        if sched:
+            b.set_schedule(**sched)
+        for s in range(4):
+            infos = b.round()
+            for r in range(len(runs)):
+                assert b.status(r) == A.OK
+                _same_as_oracle(b.population(r), infos[r], refs[r], s, (runs[r].name, s, flags))
 
 
 @pytest.mark.parametrize("flags", [0, A.F_EARLY_EXIT])
@@ -157,14 +208,22 @@ def test_uneven_batch_sampled_runs_match_plain(oracle):
 
 
 def test_full_c4_batch_sampled(oracle):
-    """The benchmark's batch (96 uneven runs, 10 stages, early exit): sampled
-    runs equal the same runs alone, and sampled particles of the last stage
-    re-simulate to the same distances in the oracle."""
+    """The benchmark's batch (96 uneven runs, 10 stages, early exit): the two
+    2048-particle runs with the shortest horizons against the oracle at every
+    stage; sampled runs equal the same runs alone, and sampled particles of
+    the last stage re-simulate to the same distances in the oracle."""
     runs = W.batched_runs()
     obs = [oracle.observations(w) for w in runs]
     R = runs[0].n_rounds
+    small = sorted((i for i, w in enumerate(runs) if w.n_particles == 2048), key=lambda i: runs[i].n_days)[:2]
+    refs = {r: oracle.run(runs[r], obs[r]) for r in small}
+    assert all(ref.rc == 0 for ref in refs.values())
     with A.Batch(runs, obs, flags=A.F_EARLY_EXIT) as b:
-        infos = b.run(R)
+        infos = []
+        for s in range(R):
+            infos.append(b.round())
+            for r in small:
+                _same_as_oracle(b.population(r), infos[s][r], refs[r], s, (r, s))
         sizes = [w.n_particles * w.n_days for w in runs]
         picks = (int(np.argmin(sizes)), int(np.argmax(sizes)), 37)
         pops = {r: b.population(r) for r in picks}

@@ -3,9 +3,10 @@ workspace and stream, early exit on, library-chosen batches).
 
 C2 (P=1e7, T=120, N=131072): stages 0 and 1 are recomputed completely by the
 oracle (process pool) and compared bit for bit, including eps^1 and eps^2;
-importance weights on sampled rows within 1e-12.  C3 (P=3e8, T=180,
-N=2^20) and the largest population the library accepts (N=2^22): sampled
-stage-0 particles bit for bit, invariants of stage 1.  C5
+importance weights on sampled rows of stages 1, 5 and 9 within 1e-12.  C3
+(P=3e8, T=180, N=2^20): sampled stage-0 particles bit for bit, invariants of
+stage 1, sampled weights of stages 1 and 11.  The largest population the
+library accepts (N=2^22): sampled stage-0 particles, invariants of stage 1.  C5
 (C2 with the learned screen at the benchmark's settings): sampled
 acceptances of the first screened stage against the oracle."""
 import numpy as np
@@ -21,23 +22,53 @@ def _bits(x):
     return np.ascontiguousarray(x, dtype=np.float64).view(np.uint64)
 
 
-def _gpu_stages(w, obs, stages):
+def _gpu_stages(w, obs, stages, keep=None):
+    """Run `stages` stages at the benchmark's launch configuration; return
+    the populations of the stages in `keep` (all if None), each with its
+    distances, weights, round info and (stage >= 1) resampling law."""
     import torch
     ws_tensor, ws = A.torch_workspace(w)
     stream = torch.cuda.current_stream()
-    out = []
+    out = {}
     with A.Context(w, obs, stream=stream.cuda_stream, workspace=ws, flags=A.F_EARLY_EXIT) as ctx:
         for i in range(stages):
             info = ctx.round()
+            if keep is not None and i not in keep:
+                continue
             pop = ctx.population()
             _, d, wt = ctx.weights()
             pop["d"], pop["W"], pop["info"] = d, wt, info
             if i >= 1:
                 pop["q"], pop["cdf"] = ctx.resampling()
-            out.append(pop)
+            out[i] = pop
     torch.cuda.synchronize()
     del ws_tensor
     return out
+
+
+def _check_weights_sampled(oracle, g, i, n_rows, seed, n_floor=64):
+    """Log-weights of stage i on sampled rows -- the first and last particle,
+    the largest and smallest step size, up to n_floor rows whose step size
+    sits at the 1e-8 floor (the narrowest windows), and n_rows random rows --
+    against the oracle's sum over the stage's own previous population and
+    quantised weights q, to 1e-12 absolute (so the weights themselves agree
+    to 1e-12 relative); the normalised weights are the softmax of the
+    log-weights to 1e-12 relative."""
+    st, u_prev = g[i], g[i - 1]["u"]
+    q, sig = st["q"], st["sigma"]
+    N = len(sig)
+    rng = np.random.default_rng(seed)
+    rows = set(rng.choice(N, n_rows, replace=False).tolist()) | {0, N - 1, int(np.argmax(sig)), int(np.argmin(sig))}
+    floor = np.flatnonzero(sig == 1e-8)
+    rows |= set(rng.permutation(floor)[:n_floor].tolist())
+    rows = np.array(sorted(rows))
+    want = np.array([oracle.log_weight(st["u"][k], sig[k], u_prev, q) for k in rows])
+    dl = np.abs(st["logw"][rows] - want)
+    assert dl.max() <= 1e-12, (i, int(rows[np.argmax(dl)]), float(dl.max()))
+    l = st["logw"]
+    e = np.exp(l - l.max())
+    np.testing.assert_allclose(st["W"], e / e.sum(), rtol=1e-12, atol=1e-300)
+    return len(floor)
 
 
 def test_c2_stages_0_1_bitwise(oracle):
@@ -74,13 +105,25 @@ def test_c2_stages_0_1_bitwise(oracle):
     eps2 = oracle.quantile(d1, w.surv_ratio)
     assert _bits([g[1]["info"]["eps_next"]])[0] == _bits([eps2])[0]
 
-    # importance weights on sampled rows (unnormalised log-weights) and normalisation
-    rows = np.unique(np.concatenate([[0, N - 1], np.random.default_rng(1).integers(0, N, 96)]))
+    # importance weights on sampled rows: the oracle's own particles k (bit-equal
+    # to the GPU's, as checked above) summed against the oracle's stage 0
+    rows = np.unique(np.concatenate([[0, N - 1], np.random.default_rng(1).integers(0, N, 254)]))
     for k in rows:
-        want = oracle.log_weight(acc[k][2], acc[k][3], u0, q)   # the oracle's own particle k
-        assert abs(g[1]["logw"][k] - want) <= 1e-12 * max(1.0, abs(want)), k
+        want = oracle.log_weight(acc[k][2], acc[k][3], u0, q)
+        assert abs(g[1]["logw"][k] - want) <= 1e-12, k
     assert abs(g[1]["W"].sum() - 1.0) < 1e-12
     assert np.all(g[1]["W"] >= 0)
+
+
+def test_c2_weights_late_stages(oracle):
+    """Importance weights of the benchmark run (C2, ten stages) at stages 1,
+    5 and 9, where eq. 16 has pushed many step sizes to the 1e-8 floor and the
+    per-row windows are narrowest."""
+    w = W.C2
+    obs = oracle.observations(w)
+    g = _gpu_stages(w, obs, 10, keep={0, 1, 4, 5, 8, 9})
+    n_floor = {i: _check_weights_sampled(oracle, g, i, 256, 20 + i) for i in (1, 5, 9)}
+    assert n_floor[9] > 0
 
 
 def _check_stage0_sampled(oracle, w, obs, g, seed, n_sample):
@@ -117,11 +160,16 @@ def _check_stage1_invariants(w, g):
 
 
 def test_c3_sampled_and_invariants(oracle):
+    """C3 (P = 3e8, 180 days, N = 2^20, twelve stages): sampled stage-0
+    particles bit for bit, stage-1 invariants, and sampled log-weights of
+    stages 1 and 11 against the oracle."""
     w = W.C3
     obs = oracle.observations(w)
-    g = _gpu_stages(w, obs, 2)
+    g = _gpu_stages(w, obs, 12, keep={0, 1, 10, 11})
     _check_stage0_sampled(oracle, w, obs, g, 3, 200)
     _check_stage1_invariants(w, g)
+    for i in (1, 11):
+        _check_weights_sampled(oracle, g, i, 96, 30 + i, n_floor=32)
 
 
 def test_largest_population_sampled_and_invariants(oracle):

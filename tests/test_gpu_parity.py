@@ -263,22 +263,27 @@ def test_predict_shorter_than_fitted_horizon(oracle):
 
 def test_mcmc_budget_error_leaves_context_usable(oracle):
     """A stage that cannot reach N acceptances within max_proposals returns
-    EBUDGET and leaves the last completed stage in place."""
+    EBUDGET and leaves the last completed stage in place.  The oracle, run
+    on the same configuration, says which stage runs out (here stage 1: its
+    five 64-proposal batches hold fewer than 300 acceptances)."""
     wl = W.tiny(step_schedule=W.STEP_MCMC, batch=64, mcmc_s0=0.1, mcmc_tune=3, max_proposals=320, seed=24)
     obs = oracle.observations(wl)
+    want = oracle.run(wl, obs, n_rounds=6)
+    assert want.rc == -4
+    completed = int(np.count_nonzero(want.proposals))
+    assert completed == 1
     with A.Context(wl, obs) as ctx:
-        ctx.round()
+        for i in range(completed):
+            info = ctx.round()
+            assert info["eps_next"] == want.eps_next[i]
         before = ctx.population()
-        done = 1
-        for _ in range(6):
-            try:
-                ctx.round()
-                done += 1
-            except A.AbcsmcError as e:
-                assert e.code == A.EBUDGET
-                break
-        else:
-            pytest.skip("budget never reached for this seed")
-        assert ctx.rounds_done() == done
-        if done == 1:
-            assert np.array_equal(ctx.population()["index"], before["index"])
+        with pytest.raises(A.AbcsmcError) as e:
+            ctx.round()
+        assert e.value.code == A.EBUDGET
+        assert ctx.rounds_done() == completed
+        after = ctx.population()
+        assert np.array_equal(after["index"], before["index"])
+        assert np.array_equal(_bits(after["u"]), _bits(before["u"]))
+        assert np.array_equal(_bits(after["u"]), _bits(want.u[completed - 1]))
+        _, d, wt = ctx.weights()
+        assert np.array_equal(_bits(d), _bits(want.dist[completed - 1]))

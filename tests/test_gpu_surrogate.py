@@ -60,7 +60,12 @@ def test_gradients_match_bf16_oracle(n):
     assert abs(loss - lo) <= 1e-4 * lo
     for name, (a, b) in M.offsets().items():
         rel = np.linalg.norm(g[a:b] - go[a:b]) / np.linalg.norm(go[a:b])
-        assert rel <= 1e-2, (name, rel)
+        # element-wise: no single entry off by more than 1e-3 of the tensor's scale
+        # (measured: at most 1e-4 at n = 200)
+        el = np.max(np.abs(g[a:b] - go[a:b])) / np.max(np.abs(go[a:b]))
+        print(f"gradient {name}: relative norm error {rel:.2e}, largest element error {el:.2e}", flush=True)
+        assert rel <= 1e-3, (name, rel)
+        assert el <= 1e-3, (name, el)
 
 
 def test_training_tracks_bf16_oracle():

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define ABCSMC_ABI_VERSION 3
+#define ABCSMC_ABI_VERSION 4
 #define ABCSMC_NPAR 8
 
 enum {
@@ -140,6 +140,9 @@ typedef struct {
                                      which bounds their total by 2^-53 of the row sum) */
     double mcmc_s;                /* STEP_MCMC: step size after this stage (0 otherwise) */
     double beta_b_real;           /* Beta shape b as a real number (STEP_MEANVAR / STEP_MODECONC) */
+    int64_t weight_window_terms;  /* sum over the N rows of the columns inside the row's own window (the
+                                     terms the row sums need; weight_terms - this = terms evaluated
+                                     because another row of the same wave needed them) */
 } abcsmc_round_info;
 
 typedef struct abcsmc_ctx abcsmc_ctx;
@@ -233,7 +236,10 @@ int abcsmc_simulate(const abcsmc_config* cfg, int64_t n, const double* theta, co
  *  fn 11: Beta(a, b) draw, a = param_a, b = param_b          (in: uint64[n*b]; out: double[n])
  *  fn 12: floor-normal draw                                 (in: {int64 n, double h, uint64 w}[n]; out: int64[n])
  *  fn 13: real-shape Beta draw (gamma ratio)                 (in: double[2] = {a, b}; out: double[n]; draw i
- *         uses stream (seed = param_a, particle i, round = param_b, PERTURB, attempt 0)) */
+ *         uses stream (seed = param_a, particle i, round = param_b, PERTURB, attempt 0))
+ *  fn 14: importance-weight term q_k exp(-|u_j - u_k|^2 / (2 sigma_j^2)) as the weight kernels
+ *         evaluate it (table exponential)       (in: double[18n] records {u_j[8], sigma_j, u_k[8], q_k};
+ *                                                out: double[n]) */
 int abcsmc_debug_eval(int32_t fn, int64_t n, const void* in, void* out, double param_a, int32_t param_b);
 
 /* ---------------------------------------------------------------------------

@@ -97,14 +97,32 @@ static const double LN2_LO = 0x1.a39ef35793c76p-33;
 static const double LOG2E = 1.4426950408889634;   /* nearest double to 1/ln 2 */
 static const double SQRT1_2 = 0.70710678118654757; /* nearest double to 1/sqrt 2 */
 static const double PI_2 = 1.5707963267948966;     /* nearest double to pi/2 */
+static const double SQRT1_2_M1 = -0.2928932188134524; /* SQRT1_2 - 1, exact (Sterbenz) */
 
-/* nearest double to 1/k!, k = 0..18 (k! is an exact double for k <= 18) */
-static double inv_fact(int k)
-{
-    double f = 1.0;
-    for (int i = 2; i <= k; ++i) f *= (double)i; /* exact: k! < 2^53 for k <= 18 */
-    return 1.0 / f;
-}
+/* nearest double to 1/k!, k = 0..18: each a correctly rounded quotient of
+ * two exact doubles (k! < 2^53 for k <= 18), evaluated by the compiler */
+static const double INV_FACT[19] = {
+    1.0 / 1.0,
+    1.0 / 1.0,
+    1.0 / 2.0,
+    1.0 / 6.0,
+    1.0 / 24.0,
+    1.0 / 120.0,
+    1.0 / 720.0,
+    1.0 / 5040.0,
+    1.0 / 40320.0,
+    1.0 / 362880.0,
+    1.0 / 3628800.0,
+    1.0 / 39916800.0,
+    1.0 / 479001600.0,
+    1.0 / 6227020800.0,
+    1.0 / 87178291200.0,
+    1.0 / 1307674368000.0,
+    1.0 / 20922789888000.0,
+    1.0 / 355687428096000.0,
+    1.0 / 6402373705728000.0
+};
+static double inv_fact(int k) { return INV_FACT[k]; }
 
 /* exp(x): k = rint(x/ln2), r = x - k ln2 (two-part, Cody & Waite),
  * exp(r) = sum_{i=0}^{13} r^i/i! by Horner with fma, result 2^k exp(r).
@@ -123,12 +141,29 @@ double ref_exp(double x)
     return ldexp(p, (int)k);
 }
 
+/* nearest doubles to 1/(2j+1), j = 0..11 (correctly rounded quotients,
+ * evaluated by the compiler) */
+static const double INV_ODD[12] = {
+    1.0 / 1.0,
+    1.0 / 3.0,
+    1.0 / 5.0,
+    1.0 / 7.0,
+    1.0 / 9.0,
+    1.0 / 11.0,
+    1.0 / 13.0,
+    1.0 / 15.0,
+    1.0 / 17.0,
+    1.0 / 19.0,
+    1.0 / 21.0,
+    1.0 / 23.0
+};
+
 /* atanh series tail: R(z) = z/3 + z^2/5 + ... + z^11/23, z = s^2, so that
- * 2 atanh(s) = 2 (s + s R(z)).  Coefficients: nearest doubles to 1/(2j+1). */
+ * 2 atanh(s) = 2 (s + s R(z)). */
 static double atanh_tail(double z)
 {
-    double q = 1.0 / 23.0;
-    for (int j = 10; j >= 1; --j) q = fma(q, z, 1.0 / (double)(2 * j + 1));
+    double q = INV_ODD[11];
+    for (int j = 10; j >= 1; --j) q = fma(q, z, INV_ODD[j]);
     return z * q;
 }
 
@@ -159,7 +194,7 @@ double ref_log1p(double x)
     if (x != x) return x;
     if (x == -1.0) return -INFINITY;
     if (x < -1.0) return NAN;
-    if (x >= SQRT1_2 - 1.0 && x <= 0.41421356237309515) {
+    if (x >= SQRT1_2_M1 && x <= 0.41421356237309515) {
         double s = x / (2.0 + x);
         double R = atanh_tail(s * s);
         return 2.0 * (s + s * R);

@@ -61,44 +61,50 @@ def lib():
     global _lib
     if _lib is None:
         build()
-        L = C.CDLL(LIB, mode=os.RTLD_LOCAL)
-        d, i64, u64, i32, u32, vp = C.c_double, C.c_int64, C.c_uint64, C.c_int32, C.c_uint32, C.c_void_p
-        sig = {
-            "ref_philox4x32_10": (None, [vp, vp, vp]),
-            "ref_word": (u64, [u64, u32, u32, u32, u32, u32]),
-            "ref_words": (None, [u64, u32, u32, u32, u32, u32, vp]),
-            "ref_u01": (d, [u64]),
-            "ref_exp": (d, [d]), "ref_expm1": (d, [d]), "ref_log": (d, [d]), "ref_log1p": (d, [d]),
-            "ref_map": (None, [i32, vp, vp, i64]),
-            "ref_box_muller_many": (None, [vp, vp, i64]),
-            "ref_binomial": (i64, [i64, d, u64]),
-            "ref_binomial_many": (None, [vp, vp, vp, vp, i64]),
-            "ref_normal_floor": (i64, [i64, d, u64]),
-            "ref_beta_int": (d, [d, i32, vp]),
-            "ref_beta_many": (None, [d, i32, vp, vp, i64]),
-            "ref_simulate": (None, [vp, vp, vp, u64, u32, u32, vp]),
-            "ref_distance": (d, [i32, vp, vp]),
-            "ref_quantile": (d, [vp, i64, d]),
-            "ref_resample_weights": (i64, [vp, i64, d, vp, vp]),
-            "ref_parent": (i64, [vp, i64, u64]),
-            "ref_perturb": (i32, [vp, u32, u32, vp, vp, i64, d, i32, vp, vp, vp]),
-            "ref_prior_draw": (None, [vp, u32, vp]),
-            "ref_sim_distance": (d, [vp, vp, vp, u32, u32, vp]),
-            "ref_log_weight": (d, [vp, d, vp, vp, i64]),
-            "ref_normalise": (d, [vp, i64, vp]),
-            "ref_run": (i32, [vp, vp, i32, vp]),
-            "ref_mcmc_update": (d, [d, i64, i64, i64]),
-            "ref_beta_general_many": (None, [d, d, u64, u32, u32, u32, vp, i64]),
-            "ref_gamma_many": (None, [d, u64, u32, u32, u32, vp, i64]),
-            "ref_beta_shape_real": (None, [vp, i32, d, d, vp, vp]),
-            "ref_accept_count": (i64, [vp, vp, vp, d, u32, u32, i64]),
-        }
-        for name, (res, args) in sig.items():
-            f = getattr(L, name)
-            f.restype = res
-            f.argtypes = args
-        _lib = L
+        _lib = bind(C.CDLL(LIB, mode=os.RTLD_LOCAL))
     return _lib
+
+
+def bind(L):
+    """Set the argument and result types of the oracle's exported functions
+    on a loaded library (this one, or the op-counting build of the same
+    source)."""
+    d, i64, u64, i32, u32, vp = C.c_double, C.c_int64, C.c_uint64, C.c_int32, C.c_uint32, C.c_void_p
+    sig = {
+        "ref_philox4x32_10": (None, [vp, vp, vp]),
+        "ref_word": (u64, [u64, u32, u32, u32, u32, u32]),
+        "ref_words": (None, [u64, u32, u32, u32, u32, u32, vp]),
+        "ref_u01": (d, [u64]),
+        "ref_exp": (d, [d]), "ref_expm1": (d, [d]), "ref_log": (d, [d]), "ref_log1p": (d, [d]),
+        "ref_map": (None, [i32, vp, vp, i64]),
+        "ref_box_muller_many": (None, [vp, vp, i64]),
+        "ref_binomial": (i64, [i64, d, u64]),
+        "ref_binomial_many": (None, [vp, vp, vp, vp, i64]),
+        "ref_normal_floor": (i64, [i64, d, u64]),
+        "ref_beta_int": (d, [d, i32, vp]),
+        "ref_beta_many": (None, [d, i32, vp, vp, i64]),
+        "ref_simulate": (None, [vp, vp, vp, u64, u32, u32, vp]),
+        "ref_distance": (d, [i32, vp, vp]),
+        "ref_quantile": (d, [vp, i64, d]),
+        "ref_resample_weights": (i64, [vp, i64, d, vp, vp]),
+        "ref_parent": (i64, [vp, i64, u64]),
+        "ref_perturb": (i32, [vp, u32, u32, vp, vp, i64, d, i32, vp, vp, vp]),
+        "ref_prior_draw": (None, [vp, u32, vp]),
+        "ref_sim_distance": (d, [vp, vp, vp, u32, u32, vp]),
+        "ref_log_weight": (d, [vp, d, vp, vp, i64]),
+        "ref_normalise": (d, [vp, i64, vp]),
+        "ref_run": (i32, [vp, vp, i32, vp]),
+        "ref_mcmc_update": (d, [d, i64, i64, i64]),
+        "ref_beta_general_many": (None, [d, d, u64, u32, u32, u32, vp, i64]),
+        "ref_gamma_many": (None, [d, u64, u32, u32, u32, vp, i64]),
+        "ref_beta_shape_real": (None, [vp, i32, d, d, vp, vp]),
+        "ref_accept_count": (i64, [vp, vp, vp, d, u32, u32, i64]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
 
 
 def _p(a: np.ndarray):

@@ -20,7 +20,7 @@ from . import workloads as W
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libabcsmc_hip.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 OK, EINVAL, ENOMEM, EDEVICE, EBUDGET, ESTATE, EDEGENERATE = 0, -1, -2, -3, -4, -5, -6
 F_EARLY_EXIT = 1
 F_STEP_IS_VARIANCE = 2
@@ -80,6 +80,7 @@ class RoundInfo(C.Structure):
         ("ms_total", C.c_double), ("ms_k_propose", C.c_double), ("ms_k_weights", C.c_double),
         ("n_k_propose", C.c_int64), ("sim_days", C.c_int64), ("weight_pairs", C.c_int64),
         ("weight_terms", C.c_int64), ("mcmc_s", C.c_double), ("beta_b_real", C.c_double),
+        ("weight_window_terms", C.c_int64),
     ]
 
     def as_dict(self):

@@ -71,7 +71,7 @@ struct BState {
     int32_t dstar;     // sort coordinate of the weight window (largest column variance)
     int32_t pad_;
     unsigned long long issued, completed, done_acc, accepted, proposals, invalid, attempts, days,
-        survivors, fallback, limit, stages_done, terms;
+        survivors, fallback, limit, stages_done, terms, window_terms;
 };
 
 struct BGlobal {

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void begin_kernel(BatchArgs a)
         }
         S.nxt = stage == 0 ? 0 : 1 - S.cur;
         S.issued = S.completed = S.done_acc = S.accepted = S.proposals = 0;
-        S.invalid = S.attempts = S.days = S.survivors = S.fallback = S.terms = 0;
+        S.invalid = S.attempts = S.days = S.survivors = S.fallback = S.terms = S.window_terms = 0;
         const double rate = S.rate > 0.01 ? S.rate : 0.01;
         unsigned long long lim = stage == 0
                                      ? (unsigned long long)((R.N + kChunkP - 1) / kChunkP)
@@ -439,6 +439,7 @@ using wterm::lower_index;
 using wterm::sigma_half_octave;
 using wterm::wave_max;
 using wterm::wave_min;
+using wterm::wave_sum_u64;
 
 // One block per run: variance of each coordinate over the run's columns.
 __global__ __launch_bounds__(kBlock) void bwdim_kernel(BatchArgs a)
@@ -541,14 +542,20 @@ __global__ __launch_bounds__(kWeightRows) void bwindow_kernel(BatchArgs a)
     if (S.failed) return;
     const int nx = S.nxt;
     const int rr = fb.y * kWeightRows + threadIdx.x;
+    const int M = (int)S.survivors;
+    const double* sk = a.skey + R.off;
     double lo = __builtin_inf(), hi = -__builtin_inf();
+    unsigned long long own = 0;  // columns of this row's own window
     if (rr < R.N) {
         const size_t j = (size_t)(a.rowkeys[R.off + rr] & 0xFFFFFull);
         const double W = a.rwin[R.off + j];
         const double x = R.u[nx][j * kNP + S.dstar];
         lo = x - W;
         hi = x + W;
+        own = (unsigned long long)(lower_index(sk, M, hi, true) - lower_index(sk, M, lo, false));
     }
+    own = wave_sum_u64(own);
+    if ((threadIdx.x & (kWave - 1)) == 0 && own) atomicAdd(&a.st[fb.x].window_terms, own);
     lo = wave_min(lo);
     hi = wave_max(hi);
     if ((threadIdx.x & (kWave - 1)) == 0) {
@@ -561,8 +568,6 @@ __global__ __launch_bounds__(kWeightRows) void bwindow_kernel(BatchArgs a)
             lo = slo[q] < lo ? slo[q] : lo;
             hi = shi[q] > hi ? shi[q] : hi;
         }
-        const int M = (int)S.survivors;
-        const double* sk = a.skey + R.off;
         a.win[R.rb0 + fb.y] = make_int2(lower_index(sk, M, lo, false), lower_index(sk, M, hi, true));
     }
 }

@@ -600,6 +600,7 @@ int abcsmc_batch_round(abcsmc_batch* b, abcsmc_round_info* infos)
             I.sim_days = (int64_t)S.days;
             I.weight_pairs = stage == 0 ? 0 : (int64_t)b->cfgs[r].n_particles * (int64_t)S.survivors;
             I.weight_terms = (int64_t)S.terms;
+            I.weight_window_terms = (int64_t)S.window_terms;
         }
     }
     return ABCSMC_OK;

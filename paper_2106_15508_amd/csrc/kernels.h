@@ -34,6 +34,7 @@ struct StageCounters {
     unsigned long long fallback;   // 1 if the prior set used d <= eps (no d < eps)
     unsigned long long days;       // proposal-days simulated over the batches run so far
     unsigned long long terms;      // importance-weight terms evaluated (inside the windows)
+    unsigned long long window_terms;  // sum over rows of the row's own window (terms the rows need)
 };
 
 // Population of one stage, array-of-structures for the per-particle gathers.
@@ -140,6 +141,7 @@ struct WeightArgs {
     int2* win;              // per row block: sorted column range [first, end) of its window
     int32_t cols_per_chunk; // columns per grid-y chunk of a window
     unsigned long long* terms;  // device counter of evaluated terms
+    unsigned long long* window_terms;  // device counter: sum over rows of the row's own window
     // per-row window half-widths from each row's parent term
     const int32_t* parent;  // N parent indices into the previous population
     const double* u_prev;   // previous population, n_prev x 8
@@ -157,6 +159,8 @@ struct WeightArgs {
 void weight_exp_constants(double ex[7]);
 // Write the kWeightTab table entries 2^(i/1024) to tab (device memory).
 void launch_weight_table(double* tab, hipStream_t s);
+// Test hook: n importance-weight terms, records {u_j[8], sigma_j, u_k[8], q_k}.
+void launch_wterm_debug(int64_t n, const double* in, double* out, hipStream_t s);
 
 // Bitonic sort of 64-bit keys (length a power of two >= 2048).
 size_t sort_padded_size(size_t n);
@@ -197,9 +201,10 @@ struct TrajArgs {
 };
 
 void launch_propose(const ProposeArgs& a, bool round0, hipStream_t s);
-// Largest first batch of a stage without a measured acceptance rate: 768
-// proposals per compute unit of the current device (three 64-lane waves per
-// SIMD, a round and a half of the proposal kernel's resident waves).
+// Largest first batch of a stage without a measured acceptance rate: one
+// round of the proposal kernel's resident waves on the current device (its
+// occupancy in workgroups per compute unit x the compute units), so a first
+// batch never leaves lanes of a second round to run on a mostly idle chip.
 int64_t propose_first_batch_lanes();
 void launch_compact(const CompactArgs& a, hipStream_t s);
 void launch_resample(const ResampleArgs& a, hipStream_t s);

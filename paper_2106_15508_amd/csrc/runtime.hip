@@ -487,6 +487,7 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
         wa.cols_per_chunk = weight_cols_per_chunk(N);
         wa.win = x->at<int2>(x->L.win);
         wa.terms = &ctr->terms;
+        wa.window_terms = &ctr->window_terms;
         wa.M = &ctr->survivors;
         wa.partial = x->at<double>(x->L.wpart);
         wa.logw = dst.logw;
@@ -527,9 +528,9 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
     HIPCHK(x, hipGetLastError());
     HIPCHK(x, hipEventRecord(x->ev[4], s));
     double hs[2] = {0, 0};
-    unsigned long long hterms = 0;
+    unsigned long long hterms[2] = {0, 0};  // terms, window_terms (adjacent counters)
     HIPCHK(x, hipMemcpyAsync(hs, scal, sizeof hs, hipMemcpyDeviceToHost, s));
-    HIPCHK(x, hipMemcpyAsync(&hterms, &ctr->terms, sizeof hterms, hipMemcpyDeviceToHost, s));
+    HIPCHK(x, hipMemcpyAsync(hterms, &ctr->terms, sizeof hterms, hipMemcpyDeviceToHost, s));
     HIPCHK(x, hipStreamSynchronize(s));
 
     // commit the stage
@@ -566,7 +567,8 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
         I.n_k_propose = batches;
         I.sim_days = (int64_t)hc.days;
         I.weight_pairs = weighted ? (int64_t)N * (int64_t)hc.survivors : 0;
-        I.weight_terms = (int64_t)hterms;
+        I.weight_terms = (int64_t)hterms[0];
+        I.weight_window_terms = (int64_t)hterms[1];
         I.mcmc_s = mcmc ? x->mcmc_s : 0.0;
         I.beta_b_real = general ? bb_real : (double)bb;
     }
@@ -785,7 +787,7 @@ int abcsmc_simulate(const abcsmc_config* cfg, int64_t n, const double* theta, co
 
 int abcsmc_debug_eval(int32_t fn, int64_t n, const void* in, void* out, double param_a, int32_t param_b)
 {
-    if (n < 1 || !in || !out || fn < 0 || fn > 13) return fail(nullptr, ABCSMC_EINVAL, "bad debug_eval arguments");
+    if (n < 1 || !in || !out || fn < 0 || fn > 14) return fail(nullptr, ABCSMC_EINVAL, "bad debug_eval arguments");
     if (fn == 13 && (!(param_a >= 0.0) || param_a > 9007199254740992.0))
         return fail(nullptr, ABCSMC_EINVAL, "seed must be an integer-valued double in [0, 2^53]");
     if (fn == 11 && (param_b < 1 || param_b > 128)) return fail(nullptr, ABCSMC_EINVAL, "beta b out of range");
@@ -797,6 +799,7 @@ int abcsmc_debug_eval(int32_t fn, int64_t n, const void* in, void* out, double p
     case 10: case 12: in_b = 24 * n; out_b = 8 * n; break;
     case 11: in_b = 8 * (size_t)n * param_b; out_b = 8 * n; break;
     case 13: in_b = 16; out_b = 8 * n; break;
+    case 14: in_b = 18 * 8 * (size_t)n; out_b = 8 * n; break;
     default: in_b = 8 * n; out_b = 8 * n; break;
     }
     void *din = nullptr, *dout = nullptr;

@@ -184,10 +184,15 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBloc
 
 int64_t propose_first_batch_lanes()
 {
-    int dev = 0, cus = 0;
+    int dev = 0, cus = 0, blocks = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
-    return (int64_t)cus * 768;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, propose_kernel<false, 0>, kBlock, 0) != hipSuccess ||
+        blocks < 1) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return (int64_t)cus * blocks * kBlock;
 }
 
 void launch_propose(const ProposeArgs& a, bool round0, hipStream_t s)
@@ -219,6 +224,10 @@ void launch_simulate_traj(const TrajArgs& a, hipStream_t s)
 void launch_debug_eval(int32_t fn, int64_t n, const void* in, void* out, double pa, int32_t pb,
                        hipStream_t s)
 {
+    if (fn == 14) {
+        launch_wterm_debug(n, (const double*)in, (double*)out, s);
+        return;
+    }
     hipLaunchKernelGGL(debug_eval_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, fn, n, in, out, pa, pb);
 }
 

@@ -238,6 +238,7 @@ using wterm::lower_index;
 using wterm::sigma_half_octave;
 using wterm::wave_max;
 using wterm::wave_min;
+using wterm::wave_sum_u64;
 
 // ---- windowed evaluation -------------------------------------------------
 // Row j only needs the columns whose coordinate d* lies within its
@@ -349,14 +350,19 @@ __global__ __launch_bounds__(kWeightRows) void wwindow_kernel(WeightArgs a)
     __shared__ double slo[kWeightRows / kWave], shi[kWeightRows / kWave];
     const int r = blockIdx.x * kWeightRows + threadIdx.x;
     const int ds = *a.dstar;
+    const int M = (int)*a.M;
     double lo = __builtin_inf(), hi = -__builtin_inf();
+    unsigned long long own = 0;  // columns of this row's own window
     if (r < a.N) {
         const size_t j = (size_t)(a.rowkeys[r] & 0xFFFFFFFFull);
         const double R = a.rwin[j];
         const double x = a.u[j * kNP + ds];
         lo = x - R;
         hi = x + R;
+        own = (unsigned long long)(lower_index(a.skey, M, hi, true) - lower_index(a.skey, M, lo, false));
     }
+    own = wave_sum_u64(own);
+    if ((threadIdx.x & (kWave - 1)) == 0 && own) atomicAdd(a.window_terms, own);
     lo = wave_min(lo);
     hi = wave_max(hi);
     if ((threadIdx.x & (kWave - 1)) == 0) {
@@ -371,7 +377,6 @@ __global__ __launch_bounds__(kWeightRows) void wwindow_kernel(WeightArgs a)
         }
         lo = slo[0] < lo ? slo[0] : lo;
         hi = shi[0] > hi ? shi[0] : hi;
-        const int M = (int)*a.M;
         a.win[blockIdx.x] = make_int2(lower_index(a.skey, M, lo, false), lower_index(a.skey, M, hi, true));
     }
 }
@@ -422,6 +427,29 @@ __global__ __launch_bounds__(kBlock) void wtable_kernel(double* tab)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i < wterm::kTab) tab[i] = wterm::table_entry(i);
+}
+
+// Test hook: one importance-weight term per record {u_j[8], sigma_j, u_k[8],
+// q_k}, by the weight kernels' own term code (table exponential from LDS,
+// scaled by the row's c_j), accumulated as the first term of a row sum.
+__global__ __launch_bounds__(kBlock) void wterm_debug_kernel(int64_t n, const double* in, double* out, WeightArgs a)
+{
+    __shared__ double T[wterm::kTab];
+    for (int i = threadIdx.x; i < wterm::kTab; i += kBlock) T[i] = wterm::table_entry(i);
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double* r = in + (size_t)i * 18;
+    double uj[kNP];
+    wterm::Col c;
+#pragma unroll
+    for (int d = 0; d < kNP; ++d) {
+        uj[d] = r[d];
+        c.u[d] = r[9 + d];
+    }
+    c.q = r[17];
+    const double cj = wterm::row_scale(r[8], a.ex);
+    out[i] = __builtin_fma(c.q, wterm::term_exp(uj, cj, c, T, a.ex), 0.0);
 }
 
 __global__ __launch_bounds__(kBlock) void weights_finalize_kernel(WeightArgs a)
@@ -686,6 +714,13 @@ void launch_weights_window(const WeightArgs& a, hipStream_t s)
     launch_sort_u64_pair(a.colkeys, a.rowkeys, a.npad, s);
     hipLaunchKernelGGL(wcolgather_kernel, dim3(blocks_of(a.N, kBlock)), b, 0, s, a);
     hipLaunchKernelGGL(wwindow_kernel, dim3(blocks_of(a.N, kWeightRows)), dim3(kWeightRows), 0, s, a);
+}
+
+void launch_wterm_debug(int64_t n, const double* in, double* out, hipStream_t s)
+{
+    WeightArgs a{};
+    weight_exp_constants(a.ex);
+    hipLaunchKernelGGL(wterm_debug_kernel, dim3(blocks_of(n, kBlock)), dim3(kBlock), 0, s, n, in, out, a);
 }
 
 void launch_weight_table(double* tab, hipStream_t s)

@@ -22,8 +22,9 @@ constexpr int kTile = 256;  // columns per skip-test tile
 // into the running sum.  There is no cut-off: a term with
 // exponent below -708 comes out as 0 or a subnormal-size value, which cannot
 // change a row sum (every row holds its own parent's term, >= e^-185) -- the
-// sums are those of the exact-zero convention.  For t below -2^31 the integer
-// conversion saturates and 2^(k >> 10) underflows to 0.
+// sums are those of the exact-zero convention.  For t below -2^31 (every far
+// column of a row whose sigma is near the 1e-8 floor) the integer conversion
+// saturates (cvt_i32_sat) and 2^(k >> 10) underflows to 0.
 constexpr int kTabBits = 10;
 constexpr int kTab = 1 << kTabBits;
 
@@ -44,6 +45,17 @@ __device__ __forceinline__ Col load_col(const_col_ptr cols, int k)
     return c;
 }
 
+// k = rint(t) as an int32, saturating: v_cvt_i32_f64 clamps an input outside
+// the int32 range to INT32_MIN / INT32_MAX by its definition, where a C++
+// conversion of such a value would be undefined.  One instruction, as the
+// plain conversion compiles to.
+__device__ __forceinline__ int cvt_i32_sat(double x)
+{
+    int r;
+    asm("v_cvt_i32_f64 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 // exp of the term (without q): with f = t - k in [-1/2, 1/2] and L = ln2/1024,
 // e^(f L) = 1 + f (L + f (L^2/2 + f L^3/6)); ex[0..2] = L, L^2/2, L^3/6
 // (kernel arguments: SGPRs).
@@ -59,7 +71,7 @@ __device__ __forceinline__ double term_exp(const double* uj, double cj, const Co
     const double t = D * cj;
     const double kk = __builtin_rint(t);
     const double f = t - kk;
-    const int ik = (int)kk;
+    const int ik = cvt_i32_sat(kk);
     double p = __builtin_fma(f, ex[2], ex[1]);
     p = __builtin_fma(p, f, ex[0]);
     p = __builtin_fma(p, f, 1.0);
@@ -189,6 +201,13 @@ __device__ __forceinline__ int lower_index(const double* v, int n, double x, boo
         else hi = mid;
     }
     return lo;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
 }
 
 __device__ __forceinline__ double wave_min(double v)

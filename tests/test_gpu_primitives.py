@@ -128,3 +128,45 @@ def test_general_beta_bitwise(oracle, a, b, seed, rnd):
     A.debug_eval(13, np.array([a, b]), n, got, float(seed), rnd)
     want = oracle.beta_general(a, b, seed, 0, rnd, 0, n)
     assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+def test_weight_term_against_oracle(oracle):
+    """One importance-weight term q_k exp(-|u_j - u_k|^2 / (2 sigma_j^2)) as
+    the weight kernels evaluate it (table exponential) against the oracle's
+    term: within 1.5e-15 + 2.5e-15 x relative, x = |u_j - u_k|^2 / (2 sigma_j^2)
+    (the cubic's truncation r^4/24 < 5.6e-16 and a few roundings, plus the
+    exponent's own rounding, which scales with x: the squared distance is
+    summed with fused multiply-adds on one side and separate roundings on
+    the other, at most 16 roundings of 1.1e-16 between them, and the scaling
+    adds four more), where the oracle's term is at least 1e-300;
+    exactly 0 where the exponent is below -2^31 in units of ln2/1024 (a
+    sigma at the 1e-8 floor and a column 0.01 or more away: the integer
+    conversion saturates instead of being undefined); below 1e-300 wherever
+    the oracle's term is 0."""
+    rng = np.random.default_rng(14)
+    n = 30000
+    uj = rng.uniform(size=(n, 8))
+    sig = 10 ** rng.uniform(-3, -0.3, n)
+    uk = np.clip(uj + sig[:, None] * rng.normal(0, 1, (n, 8)) * rng.uniform(0.1, 8, (n, 1)), 0, 1)
+    far = n - 4000
+    sig[far:] = 1e-8                                   # floor: t = -D 1024/(2e-16 ln 2) ~ -1e18 .. -1e20
+    uk[far:] = np.clip(uj[far:] + rng.choice([-1, 1], (4000, 8)) * rng.uniform(0.01, 0.5, (4000, 8)), 0, 1)
+    q = rng.integers(1, 2**40, n).astype(np.float64)
+    rec = np.concatenate([uj, sig[:, None], uk, q[:, None]], axis=1)
+    got = _ev(14, np.ascontiguousarray(rec), n, np.float64, n)
+    want = np.array([q[i] * oracle.fmap("exp", [-(float(((uj[i] - uk[i]) ** 2).sum()) / (2.0 * (sig[i] * sig[i])))])[0]
+                     for i in range(n)])
+    D = ((uj - uk) ** 2).sum(1)
+    t = -D * (1024 / np.log(2)) / (2 * sig * sig)
+    assert np.all(t[far:] < -2.0**31)
+    assert np.all(got[far:] == 0.0)
+    big = want >= 1e-300
+    assert big.sum() > 10000
+    rel = np.abs(got[big] - want[big]) / want[big]
+    x = D[big] / (2 * sig[big] * sig[big])
+    ratio = rel / (1.5e-15 + 2.5e-15 * x)
+    w = int(np.argmax(ratio))
+    print("weight term: largest relative error %.2e (x = %.1f); worst against the bound: %.2e at x = %.2f"
+          % (rel.max(), x[np.argmax(rel)], rel[w], x[w]), flush=True)
+    assert ratio.max() <= 1.0, (rel[w], x[w])
+    assert np.all(got[~big] < 1e-300) and np.all(got >= 0)

@@ -55,3 +55,78 @@ def stage(w, obs, rnd: int, u_prev, cdf, beta_a: float, beta_b: int, js: Sequenc
     with _pool(workers) as p:
         parts = p.map(_stage, jobs)
     return [r for part in parts for r in part]
+
+
+# ------------------------------------------------------------------ timing
+# The CPU-baseline leg of the benchmark times the oracle, as it stands, on
+# per-stage samples of the same work: proposals of stage i (perturbation
+# attempts, full simulation, distance) and importance-weight rows of stage i
+# against stage i-1.
+
+def reference_run(w, n_ref: int):
+    """A run of workload w's model with N = n_ref: the populations whose
+    proposals and weight rows are timed."""
+    from oracle import ref
+    wr = w.with_(n_particles=n_ref)
+    obs = ref.observations(wr)
+    run = ref.run(wr, obs)
+    if run.rc != 0:
+        raise RuntimeError(f"reference run failed: {run.rc}")
+    return wr, obs, run
+
+
+def _time_stages(args):
+    """Seconds spent on proposals j0 .. j0+n_prop-1 of every stage and on
+    weight rows r0 .. r0+n_rows-1 of every stage >= 1; returns per-stage
+    (proposals, simulated, seconds) and (rows, terms, seconds)."""
+    import time
+    from oracle import ref
+    wr, obs, run, j0, n_prop, r0, n_rows = args
+    out = []
+    for i in range(wr.n_rounds):
+        if i > 0:
+            q, Cc, _ = ref.resample_weights(run.dist[i - 1], run.eps[i])
+        t0 = time.perf_counter()
+        sim = 0
+        for j in range(j0, j0 + n_prop):
+            if i == 0:
+                u, a = ref.prior_draw(wr, j), 1
+            else:
+                a, u, _, _ = ref.perturb(wr, i, j, run.u[i - 1], Cc, run.beta_a[i], int(run.beta_b[i]))
+            if a > 0:
+                ref.sim_distance(wr, obs, u, i, j)
+                sim += 1
+        t_sim = time.perf_counter() - t0
+        rows = terms = 0
+        t_w = 0.0
+        if i > 0:
+            # the previous population repeated 32 times: the same distances per
+            # term, with the per-call overhead spread over 32x more columns
+            N = len(run.sigma[i])
+            up = np.ascontiguousarray(np.tile(run.u[i - 1], (32, 1)))
+            qq = np.ascontiguousarray(np.tile(q, 32))
+            t0 = time.perf_counter()
+            for k in range(r0, r0 + n_rows):
+                ref.log_weight(run.u[i][k % N], run.sigma[i][k % N], up, qq)
+            t_w = time.perf_counter() - t0
+            rows = n_rows
+            terms = n_rows * int(np.count_nonzero(qq))
+        out.append((n_prop, sim, t_sim, rows, terms, t_w))
+    return out
+
+
+def time_stages(wr, obs, run, n_prop: int, n_rows: int, workers: int = 1):
+    """Per-stage oracle timing on `workers` processes, each on its own
+    proposal indices and weight rows.  Returns (per-stage totals summed over
+    the workers, wall seconds)."""
+    import time
+    jobs = [(wr, obs, run, 10_000_000 + k * n_prop, n_prop, k * n_rows, n_rows) for k in range(workers)]
+    t0 = time.perf_counter()
+    if workers == 1:
+        parts = [_time_stages(jobs[0])]
+    else:
+        with _pool(workers) as p:
+            parts = p.map(_time_stages, jobs)
+    wall = time.perf_counter() - t0
+    tot = [tuple(sum(p[i][k] for p in parts) for k in range(6)) for i in range(wr.n_rounds)]
+    return tot, wall

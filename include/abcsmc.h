@@ -320,7 +320,7 @@ const char* abcsmc_batch_last_error(const abcsmc_batch* b);
 typedef struct {
     int64_t n_train;     /* prior simulations of the initial fit; 0 = 2^20; <= 2^24 */
     int32_t epochs;      /* passes over them; 0 = 4; < 0: none (random network) */
-    int32_t batch;       /* minibatch rows; 0 = 8192; <= 16384 */
+    int32_t batch;       /* minibatch rows; 0 = 8192; <= 65536 */
     double lr;           /* Adam step; 0 = 1e-3 */
     double keep_frac;    /* fraction of the first batch kept by score (sets tau); 0 = 0.1; in (0, 1] */
     double audit_rho;    /* audit probability of a proposal with score > tau; 0 = 0.01; in (0, 1] */
@@ -387,7 +387,7 @@ int abcsmc_mlp_forward(const float* params, int64_t n, const float* x, float* ou
  * stream).  Results are bit-identical to abcsmc_mlp_forward's. */
 int abcsmc_mlp_forward_noalloc(const float* params, int64_t n, const float* x, float* out, void* stream);
 /* Gradient of the loss mean over n x 3 of (out - y)^2 with respect to the
- * parameters (same layout), and the loss; 1 <= n <= 16384. */
+ * parameters (same layout), and the loss; 1 <= n <= 65536. */
 int abcsmc_mlp_gradients(const float* params, int64_t n, const float* x, const float* y, float* grad,
                          double* loss);
 /* epochs passes of minibatch Adam (fresh state) over (x, y) in row order,

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libabcsmc_hip.so")
-SOURCES = ["sim.hip", "smc.hip", "sort.hip", "runtime.hip", "batch.hip", "batch_rt.hip", "mlp.hip", "screen.hip",
+SOURCES = ["sim.hip", "smc.hip", "sort.hip", "runtime.hip", "batch.hip", "batch_rt.hip", "mlp.hip", "train.hip", "screen.hip",
            "surrogate_rt.hip", "predict.hip", "checkpoint.hip"]
 
 HIPCC_FLAGS = [

@@ -1,5 +1,5 @@
-// mlp.h -- surrogate network: sizes, GEMM arguments, activation buffers and
-// the screening-stage kernels.
+// mlp.h -- surrogate network: sizes, the training step's buffers and the
+// screening-stage kernels.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,47 +12,52 @@ namespace abcsmc {
 constexpr int kIn = 8, kH = 256, kOut = 3;
 constexpr int kMlpParams = kH * kIn + kH + kH * kH + kH + kH * kH + kH + kOut * kH + kOut;  // 134659
 
-enum : int32_t { kStore = 0, kGelu = 1, kGeluGrad = 2 };
+// ----------------------------------------------------------- training step
+// One minibatch step in three kernels (train.hip).  Buffers for up to kpad
+// rows (a multiple of 64); all device memory:
+//   wb  bfloat16 copy of the parameters (same flat layout; biases unused)
+//   wt  bfloat16 transposed weights for the backward products: W2^T [256][256]
+//       at kWt2, W3^T at kWt3, W4^T [256][8] (columns 3..7 zero) at kWt4
+//   ht  layer inputs, feature-major bf16: h0 [8][kpad], h1, h2, h3 [256][kpad]
+//   gt  layer gradients, feature-major bf16: g1, g2, g3 [256][kpad], g4 [3][kpad]
+//   dbp bias-gradient sums per 32-row block, slot-major: slot s (kBiasGrads
+//       slots) of block b at dbp[s * (kpad / 32) + b]
+//   wpart weight-gradient sums per row slice, kWpartStride floats per slice
+constexpr int kWt2 = 0, kWt3 = kH * kH, kWt4 = 2 * kH * kH, kWtElems = 2 * kH * kH + kH * 8;
+constexpr int kBiasGrads = 3 * kH + kOut;
+constexpr int kTrainSlices = 21;
+constexpr int kWpartStride = (kMlpParams + 63) / 64 * 64;  // floats per slice of wpart (16-byte aligned slices)
 
-struct GemmArgs {
-    const float* A;
-    const float* B;
-    float* C;
-    float* P;            // pre-activations (written by kGelu if not null, read by kGeluGrad)
-    const float* bias;   // length N or null
-    int32_t M, N, K, lda, ldb, ldc;
-    int32_t transA, transB;
-    int32_t accumulate;  // C += result
-    int32_t epi;
+struct TrainArgs {
+    const float* x;     // n x 8 inputs
+    const float* y;     // n x 3 targets
+    int32_t n;          // rows of this minibatch (<= kpad)
+    int64_t kpad;       // rows the ht / gt buffers hold
+    float* params;
+    float* grad;        // gradient out (may be null)
+    float* am;
+    float* av;
+    __bf16* wb;
+    __bf16* wt;
+    __bf16* ht;
+    __bf16* gt;
+    float* dbp;
+    float* wpart;
+    float* se;          // per-row squared error sum over the 3 outputs
 };
 
-struct MlpView {
-    float *W1, *b1, *W2, *b2, *W3, *b3, *W4, *b4;
-};
+// Row slices of the weight-gradient products for a minibatch of `rows`.
+int train_slices(int64_t rows);
+// Refresh wb and wt from params (after params changed outside a step).
+void launch_train_copies(const TrainArgs& a, hipStream_t s);
+// Loss gradient of the minibatch (to a.grad if set); with lr > 0 also the
+// Adam step number `step` and the bfloat16 copies of the updated weights.
+void launch_train_step(const TrainArgs& a, float lr, int step, hipStream_t s);
 
-// Split-K slices of the weight-gradient products (and the bias-gradient
-// partial sums): at most kSplitMax slices of up to 256 x 256.
-constexpr int kSplitMax = 32;
-constexpr int64_t kSplitFloats = (int64_t)kSplitMax * kH * kH;
-
-// Activation scratch for up to `rows` samples, plus kSplitFloats of `part`.
-struct MlpActs {
-    float *a1, *a2, *a3, *h1, *h2, *h3, *out, *d1, *d2, *d3, *part;
-};
-
-MlpView mlp_view(float* params);
-// part: split-K scratch (kSplitFloats) or null (no split).
-void launch_gemm(const GemmArgs& g, float* part, hipStream_t s);
-void launch_colsum(const float* X, int M, int N, int ld, float* out, float* part, hipStream_t s);
-void launch_mse_grad(const float* out, const float* y, int n, float* dout, float* se, hipStream_t s);
-void launch_adam(float* w, const float* g, float* m, float* v, int n, float lr, int step, hipStream_t s);
-void mlp_forward(const float* params, const float* x, int n, MlpActs& s, hipStream_t st);
 // Forward only, one fused kernel (activations in LDS): wb receives the bf16
 // copy of the parameters (kMlpParams); out n x 3 and/or score n (predicted
 // squared distance sum_c expm1(y_c)^2), either may be null.
 void mlp_infer(const float* params, __bf16* wb, const float* x, int64_t n, float* out, double* score, hipStream_t st);
-void mlp_backward(const float* params, const float* x, int n, MlpActs& s, const float* dout, float* grad,
-                  hipStream_t st);
 
 // ----------------------------------------------------------- screened stage
 

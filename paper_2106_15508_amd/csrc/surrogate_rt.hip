@@ -24,13 +24,16 @@ namespace rt {
 
 constexpr int64_t kInferRows = 65536;  // rows per call of the network hooks
 constexpr int64_t kPoolMax = (int64_t)1 << 22;
-constexpr int32_t kTrainBatchMax = 16384;
+constexpr int32_t kTrainBatchMax = 65536;
 
-// Network, its gradient and Adam state, and activations for one minibatch.
+// Network, its gradient and Adam state, and the training step's buffers for
+// minibatches of up to kpad rows.
 struct Trainer {
     float *params = nullptr, *grad = nullptr, *am = nullptr, *av = nullptr;
-    float *dout = nullptr, *se = nullptr;
-    MlpActs acts{};
+    float* se = nullptr;
+    __bf16 *wb = nullptr, *wt = nullptr, *ht = nullptr, *gt = nullptr;
+    float *dbp = nullptr, *wpart = nullptr;
+    int64_t kpad = 0;
     int64_t step = 0;
 };
 
@@ -78,17 +81,39 @@ struct Carver {
 
 void carve_trainer(Carver& c, Trainer& t, int64_t rows, int64_t se_rows)
 {
+    t.kpad = (rows + 63) / 64 * 64;
+    const int64_t blocks = t.kpad / 32;
     t.params = c.take<float>(kMlpParams);
     t.grad = c.take<float>(kMlpParams);
     t.am = c.take<float>(kMlpParams);
     t.av = c.take<float>(kMlpParams);
-    t.dout = c.take<float>((size_t)rows * kOut);
     t.se = c.take<float>((size_t)se_rows);
-    float** a[] = {&t.acts.a1, &t.acts.a2, &t.acts.a3, &t.acts.h1, &t.acts.h2,
-                   &t.acts.h3, &t.acts.d1, &t.acts.d2, &t.acts.d3};
-    for (float** p : a) *p = c.take<float>((size_t)rows * kH);
-    t.acts.out = c.take<float>((size_t)rows * kOut);
-    t.acts.part = c.take<float>((size_t)kSplitFloats);
+    t.wb = c.take<__bf16>(kMlpParams);
+    t.wt = c.take<__bf16>(kWtElems);
+    t.ht = c.take<__bf16>((size_t)(kIn + 3 * kH) * t.kpad);
+    t.gt = c.take<__bf16>((size_t)(3 * kH + kOut) * t.kpad);
+    t.dbp = c.take<float>((size_t)blocks * kBiasGrads);
+    t.wpart = c.take<float>((size_t)kTrainSlices * kWpartStride);
+}
+
+TrainArgs train_args(const Trainer& t, const float* x, const float* y, int64_t n, float* se)
+{
+    TrainArgs a{};
+    a.x = x;
+    a.y = y;
+    a.n = (int32_t)n;
+    a.kpad = t.kpad;
+    a.params = t.params;
+    a.am = t.am;
+    a.av = t.av;
+    a.wb = t.wb;
+    a.wt = t.wt;
+    a.ht = t.ht;
+    a.gt = t.gt;
+    a.dbp = t.dbp;
+    a.wpart = t.wpart;
+    a.se = se;
+    return a;
 }
 
 // `epochs` passes of minibatch Adam over (X, Y) (n rows, in order; the last
@@ -98,14 +123,11 @@ hipError_t train_epochs(Trainer& t, const float* X, const float* Y, int64_t n, i
                         float lr, double* losses, hipStream_t s)
 {
     std::vector<float> se;
+    if (epochs > 0 && n > 0) launch_train_copies(train_args(t, X, Y, 0, t.se), s);  // params may have changed
     for (int32_t e = 0; e < epochs; ++e) {
         for (int64_t off = 0; off < n; off += batch) {
-            const int b = (int)std::min<int64_t>(batch, n - off);
-            const float* xb = X + off * kIn;
-            mlp_forward(t.params, xb, b, t.acts, s);
-            launch_mse_grad(t.acts.out, Y + off * kOut, b, t.dout, t.se + off, s);
-            mlp_backward(t.params, xb, b, t.acts, t.dout, t.grad, s);
-            launch_adam(t.params, t.grad, t.am, t.av, kMlpParams, lr, (int)(++t.step), s);
+            const int64_t b = std::min<int64_t>(batch, n - off);
+            launch_train_step(train_args(t, X + off * kIn, Y + off * kOut, b, t.se + off), lr, (int)(++t.step), s);
         }
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
@@ -126,7 +148,7 @@ int check_scfg(const abcsmc_surrogate_config& c, std::string* err)
 {
     if (c.n_train < 1 || c.n_train > ((int64_t)1 << 24)) return fail(err, ABCSMC_EINVAL, "n_train must be in [1, 2^24]");
     if (c.epochs < 0 || c.epochs > 1000) return fail(err, ABCSMC_EINVAL, "epochs must be in [0, 1000]");
-    if (c.batch < 1 || c.batch > kTrainBatchMax) return fail(err, ABCSMC_EINVAL, "batch must be in [1, 16384]");
+    if (c.batch < 1 || c.batch > kTrainBatchMax) return fail(err, ABCSMC_EINVAL, "batch must be in [1, 65536]");
     if (!(c.lr > 0.0 && c.lr < 1.0)) return fail(err, ABCSMC_EINVAL, "lr must be in (0, 1)");
     if (!(c.keep_frac > 0.0 && c.keep_frac <= 1.0)) return fail(err, ABCSMC_EINVAL, "keep_frac must be in (0, 1]");
     if (!(c.audit_rho > 0.0 && c.audit_rho <= 1.0)) return fail(err, ABCSMC_EINVAL, "audit_rho must be in (0, 1]");
@@ -660,7 +682,7 @@ int abcsmc_mlp_gradients(const float* params, int64_t n, const float* xs, const 
                          double* loss)
 {
     if (!params || !xs || !ys || !grad) return fail(nullptr, ABCSMC_EINVAL, "NULL argument");
-    if (n < 1 || n > kTrainBatchMax) return fail(nullptr, ABCSMC_EINVAL, "n must be in [1, 16384]");
+    if (n < 1 || n > kTrainBatchMax) return fail(nullptr, ABCSMC_EINVAL, "n must be in [1, 65536]");
     DevBuf m;
     Trainer t;
     Carver c{nullptr};
@@ -675,9 +697,10 @@ int abcsmc_mlp_gradients(const float* params, int64_t n, const float* xs, const 
     HOOKCHK(hipMemcpy(t.params, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice));
     HOOKCHK(hipMemcpy(X, xs, (size_t)n * kIn * sizeof(float), hipMemcpyHostToDevice));
     HOOKCHK(hipMemcpy(Y, ys, (size_t)n * kOut * sizeof(float), hipMemcpyHostToDevice));
-    mlp_forward(t.params, X, (int)n, t.acts, nullptr);
-    launch_mse_grad(t.acts.out, Y, (int)n, t.dout, t.se, nullptr);
-    mlp_backward(t.params, X, (int)n, t.acts, t.dout, t.grad, nullptr);
+    TrainArgs ta = train_args(t, X, Y, n, t.se);
+    ta.grad = t.grad;
+    launch_train_copies(ta, nullptr);
+    launch_train_step(ta, 0.f, 0, nullptr);
     HOOKCHK(hipGetLastError());
     HOOKCHK(hipMemcpy(grad, t.grad, kMlpParams * sizeof(float), hipMemcpyDeviceToHost));
     if (loss) {
@@ -695,7 +718,7 @@ int abcsmc_mlp_train(float* params, int64_t n, const float* xs, const float* ys,
 {
     if (!params || !xs || !ys) return fail(nullptr, ABCSMC_EINVAL, "NULL argument");
     if (n < 1 || n > ((int64_t)1 << 24)) return fail(nullptr, ABCSMC_EINVAL, "n must be in [1, 2^24]");
-    if (batch < 1 || batch > kTrainBatchMax) return fail(nullptr, ABCSMC_EINVAL, "batch must be in [1, 16384]");
+    if (batch < 1 || batch > kTrainBatchMax) return fail(nullptr, ABCSMC_EINVAL, "batch must be in [1, 65536]");
     if (epochs < 0 || epochs > 1000) return fail(nullptr, ABCSMC_EINVAL, "epochs must be in [0, 1000]");
     if (!(lr > 0.0 && lr < 1.0)) return fail(nullptr, ABCSMC_EINVAL, "lr must be in (0, 1)");
     DevBuf m;

@@ -70,7 +70,12 @@ TRAFFIC_SOURCES = ("paper_2106_15508_amd/csrc/smc.hip", "paper_2106_15508_amd/cs
                    "paper_2106_15508_amd/csrc/sim.hip", "paper_2106_15508_amd/csrc/propose.h",
                    "paper_2106_15508_amd/build.py")
 TRAFFIC_MEASURED = {
-    # (sources, workload, kernel): FETCH_SIZE KiB x 2 + WRITE_SIZE KiB x 1 per launch
+    # (sources, workload, kernel): (FETCH_SIZE KiB x 2 + WRITE_SIZE KiB x 1) x 1024 bytes per launch,
+    # averaged over the launches of one run (commands and raw values in profiles/)
+    ("dddc6a4450cfe0f7", "c2", "weights_kernel"): 1.1746e9,
+    ("dddc6a4450cfe0f7", "c2", "propose_kernel"): 4.8978e7,
+    ("dddc6a4450cfe0f7", "c3", "weights_kernel"): 8.9099e10,
+    ("dddc6a4450cfe0f7", "c3", "propose_kernel"): 8.7435e8,
 }
 
 
@@ -360,10 +365,10 @@ def bench_batched(args, steps, warmup):
 def bench_surrogate(args, steps, warmup):
     """The headline workload with the learned screen: per step, stage 0, the
     network's initial fit on 2^22 prior simulations (2 passes, minibatch
-    8192, included in the step), then nine screened stages (keep 10% of each
-    stage's first batch by score, audit rho = 1%, screening kept on in every
-    stage).  The same steps of the plain form run beside it for the
-    comparison of throughput and posterior moments."""
+    32768, Adam step 5e-3, included in the step), then nine screened stages
+    (keep 10% of each stage's first batch by score, audit rho = 1%,
+    screening kept on in every stage).  The same steps of the plain form run
+    beside it for the comparison of throughput and posterior moments."""
     import numpy as np
     import torch
 
@@ -375,7 +380,7 @@ def bench_surrogate(args, steps, warmup):
     obs = A.observations(w)
     stream = torch.cuda.current_stream()
     flags = A.F_EARLY_EXIT if args.early_exit else 0
-    sur = dict(n_train=1 << 22, epochs=2, batch=8192, keep_frac=0.1, audit_rho=0.01, fn_max=1.0, seed=11)
+    sur = dict(n_train=1 << 22, epochs=2, batch=32768, lr=5e-3, keep_frac=0.1, audit_rho=0.01, fn_max=1.0, seed=11)
 
     def one(ctx, screened):
         ctx.reset()
@@ -431,7 +436,7 @@ def bench_surrogate(args, steps, warmup):
     return {
         "value": N * R / scr["sec"], "unit": "accepted particles/s", "steps": steps, "ms_per_step": scr["sec"] * 1e3,
         "workload": (f"c5: c2 (P={w.population}, T={w.n_days}, N={N}, stages={R}) with the learned screen: fit "
-                     "on 2^22 prior simulations x 2 passes, keep 10%, audit 1%"),
+                     "on 2^22 prior simulations x 2 passes of minibatch 32768, keep 10%, audit 1%"),
         "plain_value": N * R / plain["sec"],
         "speedup_vs_plain": plain["sec"] / scr["sec"],
         "fn_mass": [round(s["fn_mass"], 4) for s in last_s],

@@ -196,7 +196,7 @@ def test_c5_screened_stage_sampled(oracle):
     from oracle import mlp_ref as M
     w = W.C2
     obs = A.observations(w)
-    sur = dict(n_train=1 << 22, epochs=2, batch=8192, keep_frac=0.1, audit_rho=0.01, fn_max=1.0, seed=11)
+    sur = dict(n_train=1 << 22, epochs=2, batch=32768, lr=5e-3, keep_frac=0.1, audit_rho=0.01, fn_max=1.0, seed=11)
     with A.Context(w, obs, flags=A.F_EARLY_EXIT) as ctx:
         ctx.round()
         p0 = ctx.population()

@@ -46,6 +46,10 @@ struct TrainArgs {
     float* se;          // per-row squared error sum over the 3 outputs
 };
 
+// part[kSeParts] = sum of se[0..n) in double (fixed order); part holds
+// kSeParts + 1 doubles of device memory.
+constexpr int kSeParts = 256;
+void launch_se_sum(const float* se, int64_t n, double* part, hipStream_t s);
 // Row slices of the weight-gradient products for a minibatch of `rows`.
 int train_slices(int64_t rows);
 // Refresh wb and wt from params (after params changed outside a step).

@@ -33,6 +33,7 @@ struct Trainer {
     float* se = nullptr;
     __bf16 *wb = nullptr, *wt = nullptr, *ht = nullptr, *gt = nullptr;
     float *dbp = nullptr, *wpart = nullptr;
+    double* lpart = nullptr;  // loss sum: kSeParts block sums and the total
     int64_t kpad = 0;
     int64_t step = 0;
 };
@@ -94,6 +95,7 @@ void carve_trainer(Carver& c, Trainer& t, int64_t rows, int64_t se_rows)
     t.gt = c.take<__bf16>((size_t)(3 * kH + kOut) * t.kpad);
     t.dbp = c.take<float>((size_t)blocks * kBiasGrads);
     t.wpart = c.take<float>((size_t)kTrainSlices * kWpartStride);
+    t.lpart = c.take<double>(kSeParts + 1);
 }
 
 TrainArgs train_args(const Trainer& t, const float* x, const float* y, int64_t n, float* se)
@@ -122,7 +124,6 @@ TrainArgs train_args(const Trainer& t, const float* x, const float* y, int64_t n
 hipError_t train_epochs(Trainer& t, const float* X, const float* Y, int64_t n, int32_t batch, int32_t epochs,
                         float lr, double* losses, hipStream_t s)
 {
-    std::vector<float> se;
     if (epochs > 0 && n > 0) launch_train_copies(train_args(t, X, Y, 0, t.se), s);  // params may have changed
     for (int32_t e = 0; e < epochs; ++e) {
         for (int64_t off = 0; off < n; off += batch) {
@@ -132,12 +133,11 @@ hipError_t train_epochs(Trainer& t, const float* X, const float* Y, int64_t n, i
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
         if (losses) {
-            se.resize((size_t)n);
-            err = hipMemcpyAsync(se.data(), t.se, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, s);
+            double sum = 0.0;
+            launch_se_sum(t.se, n, t.lpart, s);
+            err = hipMemcpyAsync(&sum, t.lpart + kSeParts, sizeof(double), hipMemcpyDeviceToHost, s);
             if (err == hipSuccess) err = hipStreamSynchronize(s);
             if (err != hipSuccess) return err;
-            double sum = 0.0;
-            for (float v : se) sum += (double)v;
             losses[e] = n ? sum / (3.0 * (double)n) : 0.0;
         }
     }

@@ -595,7 +595,38 @@ __global__ __launch_bounds__(256) void train_copies_kernel(TrainArgs a)
     if (i < kMlpParams) a.wb[i] = to_bf16(a.params[i]);
 }
 
+// Sum of the per-row squared errors in double, in a fixed order: block b of
+// kSeParts adds rows b, b + kSeParts * 256 ... per thread, then its threads
+// by a fixed tree; one block then adds the block sums in order.
+__global__ __launch_bounds__(256) void se_part_kernel(const float* se, int64_t n, double* part)
+{
+    __shared__ double sh[256];
+    double v = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)kSeParts * 256) v += (double)se[i];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(64) void se_total_kernel(double* part)
+{
+    if (threadIdx.x != 0) return;
+    double v = 0.0;
+    for (int b = 0; b < kSeParts; ++b) v += part[b];
+    part[kSeParts] = v;
+}
+
 }  // namespace
+
+void launch_se_sum(const float* se, int64_t n, double* part, hipStream_t s)
+{
+    hipLaunchKernelGGL(se_part_kernel, dim3(kSeParts), dim3(256), 0, s, se, n, part);
+    hipLaunchKernelGGL(se_total_kernel, dim3(1), dim3(64), 0, s, part);
+}
 
 int train_slices(int64_t rows)
 {

@@ -58,8 +58,9 @@ __device__ __forceinline__ void gelu_both(float x, float& g, float& dg)
 {
     const float k1 = 2.0f * 0.7978845608028654f;  // 2c
     const float k3 = k1 * 0.044715f;              // 2c * 0.044715
+    const float l2e = 1.4426950408889634f;        // log2(e): e^{-2y} = 2^{-2y log2 e}
     const float x2 = x * x;
-    const float e = __expf(-x * fmaf(k3, x2, k1));  // e^{-2y}; +inf for large negative x (then s = 0)
+    const float e = __builtin_amdgcn_exp2f(-x * fmaf(k3 * l2e, x2, k1 * l2e));  // e^{-2y}; +inf for large negative x (then s = 0)
     const float s = __builtin_amdgcn_rcpf(1.0f + e);
     g = x * s;
     dg = fmaf(g * (1.0f - s), fmaf(3.0f * k3, x2, k1), s);
@@ -126,11 +127,16 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
     // B fragments of a 256 x kCW slice whose column c has its K values
     // contiguous at W + c * 256: all eight K steps, requested at once
     bf16x8 bw[8][kNB];
+    // lane offset of its fragments in a 256 x 256 matrix: row c0 + 16 b + lr,
+    // K offset 8 lg (the K steps are immediate offsets of 64 bytes)
+    const int wofs = (c0 + lr) * kH + 8 * lg;
     auto load_w = [&](const __bf16* W) {
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks)
+        for (int b = 0; b < kNB; ++b) {
+            const bf16x8* p = reinterpret_cast<const bf16x8*>(W + wofs + 16 * b * kH);
 #pragma unroll
-            for (int b = 0; b < kNB; ++b) bw[ks][b] = ld8(W + (int64_t)(c0 + 16 * b + lr) * kH + 32 * ks + 8 * lg);
+            for (int ks = 0; ks < 8; ++ks) bw[ks][b] = p[4 * ks];
+        }
     };
     load_w(a.wb + kOffW2);  // layer 2's fragments, in flight through layer 1
 
@@ -153,6 +159,16 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
 #pragma unroll
             for (int j = 0; j < kNB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     };
+    // forward layers start from the bias: a = bias + sum_k h_k W_ck, the sum
+    // accumulated onto it by the matrix core
+    auto bias_acc = [&](const float* bias) {
+#pragma unroll
+        for (int b = 0; b < kNB; ++b) {
+            const float bc = bias[c0 + 16 * b + lr];
+#pragma unroll
+            for (int i = 0; i < RB; ++i) acc[i][b] = f32x4{bc, bc, bc, bc};
+        }
+    };
     // acc += Hs (TR x 256) times the slice held in bw; the A fragments of K
     // step ks + 1 are read while step ks's products run (two steps' worth of
     // registers at most: the scheduling barrier keeps later reads from being
@@ -174,20 +190,20 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
             __builtin_amdgcn_sched_barrier(0);
         }
     };
-    // forward epilogue of a hidden layer: a = acc + bias, h = GELU(a);
+    // forward epilogue of a hidden layer: a = acc (bias included), h = GELU(a);
     // GELU'(a) to d, h^T to global and h to hp (bfloat16, for LDS).
-    auto fwd_epilogue = [&](const float* bias, float (&d)[RB][kNB][4], bf16x4 (&hp)[RB][kNB], __bf16* ht) {
+    auto fwd_epilogue = [&](float (&d)[RB][kNB][4], bf16x4 (&hp)[RB][kNB], __bf16* ht) {
 #pragma unroll
         for (int b = 0; b < kNB; ++b) {
             const int c = c0 + 16 * b + lr;
-            const float bc = bias[c];
+            bf16x4* hrow = reinterpret_cast<bf16x4*>(ht + (int64_t)c * kp + r0 + 4 * lg);  // + 4 i: row block i
 #pragma unroll
             for (int i = 0; i < RB; ++i) {
                 float h[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) gelu_both(acc[i][b][e] + bc, h[e], d[i][b][e]);
+                for (int e = 0; e < 4; ++e) gelu_both(acc[i][b][e], h[e], d[i][b][e]);
                 hp[i][b] = bf16x4{to_bf16(h[0]), to_bf16(h[1]), to_bf16(h[2]), to_bf16(h[3])};
-                *reinterpret_cast<bf16x4*>(ht + (int64_t)c * kp + r0 + 16 * i + 4 * lg) = hp[i][b];
+                hrow[4 * i] = hp[i][b];
             }
         }
     };
@@ -202,7 +218,7 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
 
     // ---- layer 1 (8 -> 256): one K step, K padded to 32
     {
-        zero_acc();
+        bias_acc(a.params + kOffB1);
         bf16x8 bfr[kNB];
 #pragma unroll
         for (int b = 0; b < kNB; ++b) bfr[b] = lg == 0 ? ld8(a.wb + (int64_t)(c0 + 16 * b + lr) * kIn) : zero8;
@@ -213,28 +229,28 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
             for (int b = 0; b < kNB; ++b) acc[i][b] = mfma(af, bfr[b], acc[i][b]);
         }
         bf16x4 hv[RB][kNB];
-        fwd_epilogue(a.params + kOffB1, dp[0], hv, a.ht + (int64_t)kIn * kp);
+        fwd_epilogue(dp[0], hv, a.ht + (int64_t)kIn * kp);
         store_lds(hv);
         __syncthreads();
     }
     // ---- layer 2 (256 -> 256)
     {
-        zero_acc();
+        bias_acc(a.params + kOffB2);
         product256();
         load_w(a.wb + kOffW3);  // next: layer 3
         bf16x4 hv[RB][kNB];
-        fwd_epilogue(a.params + kOffB2, dp[1], hv, a.ht + (int64_t)(kIn + kH) * kp);
+        fwd_epilogue(dp[1], hv, a.ht + (int64_t)(kIn + kH) * kp);
         __syncthreads();  // every wave has read h1
         store_lds(hv);
         __syncthreads();
     }
     // ---- layer 3 (256 -> 256)
     {
-        zero_acc();
+        bias_acc(a.params + kOffB3);
         product256();
         load_w(a.wt + kWt3);  // next: the g2 product
         bf16x4 hv[RB][kNB];
-        fwd_epilogue(a.params + kOffB3, dp[2], hv, a.ht + (int64_t)(kIn + 2 * kH) * kp);
+        fwd_epilogue(dp[2], hv, a.ht + (int64_t)(kIn + 2 * kH) * kp);
         __syncthreads();  // every wave has read h2
         store_lds(hv);
         __syncthreads();
@@ -292,12 +308,13 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
         for (int b = 0; b < kNB; ++b) {
             const int c = c0 + 16 * b + lr;
             float cs[RB][4];
+            bf16x4* grow = reinterpret_cast<bf16x4*>(gt + (int64_t)c * kp + r0 + 4 * lg);  // + 4 i: row block i
 #pragma unroll
             for (int i = 0; i < RB; ++i) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) cs[i][e] = acc[i][b][e] * d[i][b][e];
                 gp[i][b] = bf16x4{to_bf16(cs[i][0]), to_bf16(cs[i][1]), to_bf16(cs[i][2]), to_bf16(cs[i][3])};
-                *reinterpret_cast<bf16x4*>(gt + (int64_t)c * kp + r0 + 16 * i + 4 * lg) = gp[i][b];
+                grow[4 * i] = gp[i][b];
             }
             const float s = block_colsum<RB>(cs);
             if (lg == 0) a.dbp[(int64_t)(L * kH + c) * nblk + blk] = s;

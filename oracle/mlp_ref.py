@@ -11,9 +11,11 @@ Two arithmetic modes:
   * FP64 (``forward``, ``loss_grad``): the definition, in float64.
   * BF16-emulating (``forward_bf16``, ``loss_grad_bf16``): every matrix
     product rounds both operands to bfloat16 (round to nearest even) and
-    accumulates in float32 in increasing k order; everything else (bias,
-    activation, loss, bias sums) is float32.  This is the arithmetic the
-    matrix-core kernels perform, up to the order of the float32 sums.
+    accumulates in float32 in increasing k order; GELU'(a) is rounded to
+    float16 (nearest even) between the forward and the backward pass, where
+    the kernels keep it; everything else (bias, activation, loss, bias sums)
+    is float32.  This is the arithmetic the matrix-core kernels perform, up
+    to the order of the float32 sums.
 
 Inputs of the screen: x = 2u - 1 of a proposal's unit-cube coordinates;
 targets y_c = log1p(sqrt(S_c)) for the per-series sums of squares S_A, S_R,
@@ -126,6 +128,12 @@ def bf16(x) -> np.ndarray:
     return r.astype(np.uint32).view(np.float32).reshape(f.shape)
 
 
+def f16(x) -> np.ndarray:
+    """Round float32 values to IEEE binary16 (nearest, ties to even,
+    subnormals kept), returned as float32."""
+    return np.asarray(x, dtype=np.float32).astype(np.float16).astype(np.float32)
+
+
 def matmul_bf16(A, B) -> np.ndarray:
     """A (M x K) times B (K x N): bfloat16 operands, float32 sum in k order."""
     a, b = bf16(A), bf16(B)
@@ -179,11 +187,11 @@ def loss_grad_bf16(p, x, y):
     loss = float(np.sum(r.astype(np.float64) ** 2) / (3.0 * n))
     g4 = (np.float32(2.0) * r) / np.float32(3.0 * n)
     G = {"W4": matmul_bf16(g4.T, c["h3"]), "b4": _colsum32(g4)}
-    g3 = matmul_bf16(g4, P["W4"]) * _gelu_grad32(c["a3"])
+    g3 = matmul_bf16(g4, P["W4"]) * f16(_gelu_grad32(c["a3"]))
     G["W3"], G["b3"] = matmul_bf16(g3.T, c["h2"]), _colsum32(g3)
-    g2 = matmul_bf16(g3, P["W3"]) * _gelu_grad32(c["a2"])
+    g2 = matmul_bf16(g3, P["W3"]) * f16(_gelu_grad32(c["a2"]))
     G["W2"], G["b2"] = matmul_bf16(g2.T, c["h1"]), _colsum32(g2)
-    g1 = matmul_bf16(g2, P["W2"]) * _gelu_grad32(c["a1"])
+    g1 = matmul_bf16(g2, P["W2"]) * f16(_gelu_grad32(c["a1"]))
     G["W1"], G["b1"] = matmul_bf16(g1.T, c["h0"]), _colsum32(g1)
     grad = np.concatenate([G[name].ravel() for name, _ in SHAPES]).astype(np.float32)
     return loss, grad

@@ -4,15 +4,16 @@
 // FP32 accumulation.
 //
 // Rounding points are those of the per-layer products: every matrix product
-// rounds both operands to bfloat16 (nearest even) and sums in FP32; bias,
-// GELU and its derivative, the loss gradient 2 (out - y) / (3 n), the
-// elementwise products with GELU' and the bias sums are FP32; weights, their
-// gradients and the Adam moments are FP32.
+// rounds both operands to bfloat16 (nearest even) and sums in FP32; GELU'(a)
+// is kept between the passes as float16 (nearest even); bias, GELU and its
+// derivative, the loss gradient 2 (out - y) / (3 n), the elementwise products
+// with GELU' and the bias sums are FP32; weights, their gradients and the
+// Adam moments are FP32.
 //
-//   kernel 1 (train_pass_kernel): 32 rows per workgroup through the four
+//   kernel 1 (train_pass_kernel): 32 or 64 rows per workgroup through the four
 //     layers, the loss gradient, and back through the data products
-//     g_l = (g_{l+1} W_{l+1}) * GELU'(a_l), all row-local (activations in LDS,
-//     GELU' in registers).  Writes the
+//     g_l = (g_{l+1} W_{l+1}) * GELU'(a_l), all row-local (activations and
+//     GELU' in LDS).  Writes the
 //     layers' inputs h_{l-1} and gradients g_l transposed (feature-major,
 //     bfloat16) for the weight products, the per-row squared errors and the
 //     block's bias-gradient sums.
@@ -39,7 +40,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTR = 32;        // rows per workgroup of the fused pass
 constexpr int kPT = 512;       // its threads: 8 waves
 constexpr int kCW = kH / (kPT / 64);  // columns of a 256-wide layer per wave (32)
 constexpr int kNB = kCW / 16;  // 16-column blocks per wave
@@ -98,19 +98,22 @@ __device__ __forceinline__ float block_colsum(const float (&v)[RB][4])
 }
 
 // ---------------------------------------------------------------------------
-// Kernel 1.  TR = 32 rows per workgroup (a minibatch of 8192 rows fills 256
-// compute units), 8 waves (two per SIMD, to overlap one wave's latencies with
-// the other's work).  Wave w owns columns [32w, 32w + 32) of each 256-wide
-// layer for the TR rows: RB x 2 blocks of 16 x 16 (lane holds rows
-// 16i + 4 lg + e, column 16b + lr of block (i, b); lr = lane % 16,
-// lg = lane / 16).  A layer's weight fragments are all requested before the
-// previous layer's epilogue, so their L2 latency overlaps that work; GELU'(a)
-// of the three hidden layers stays in the lanes' registers until the backward
-// products.
+// Kernel 1.  TR rows per workgroup: 64 where the minibatch has rows for 256
+// such workgroups (every workgroup fetches all four weight matrices, so 64
+// rows halve the fetches per row), else 32 (8192 rows fill 256 compute
+// units).  8 waves (two per SIMD, to overlap one wave's latencies with the
+// other's work).  Wave w owns columns [32w, 32w + 32) of each 256-wide layer
+// for the TR rows: RB x 2 blocks of 16 x 16 (lane holds rows 16i + 4 lg + e,
+// column 16b + lr of block (i, b); lr = lane % 16, lg = lane / 16).  A
+// layer's weight fragments are all requested before the previous layer's
+// epilogue, so their L2 latency overlaps that work.  GELU'(a) of the three
+// hidden layers waits in LDS for the backward products, rounded to float16
+// (nearest even; two per 32-bit word, each thread its own words).
 // ---------------------------------------------------------------------------
+template <int TR>
 __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
 {
-    constexpr int TR = kTR, RB = TR / 16;  // rows, 16-row blocks
+    constexpr int RB = TR / 16;  // 16-row blocks
     __shared__ __attribute__((aligned(16))) __bf16 Hs[TR][kTP];  // h_l (forward), then g_l (backward)
     __shared__ __attribute__((aligned(16))) __bf16 Xs[TR][kXP];  // x, then g4, K padded to 32
     __shared__ float G4[TR][4];
@@ -152,12 +155,39 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
     }
 
     f32x4 acc[RB][kNB];
-    float dp[3][RB][kNB][4];  // GELU'(a_l) at this lane's elements
+    __shared__ unsigned int DPs[3][RB * kNB * 2][kPT];  // GELU'(a_l), float16 pairs
+    float dp[RB][kNB][4];  // GELU'(a_l) of the layer at hand, this lane's elements
     auto zero_acc = [&]() {
 #pragma unroll
         for (int i = 0; i < RB; ++i)
 #pragma unroll
             for (int j = 0; j < kNB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    };
+    // GELU'(a_l) to and from LDS as float16 (round to nearest even), the
+    // pairs (e, e + 1) of a lane packed in one word at [l][pair][thread]
+    auto store_dp = [&](int L) {
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+            for (int b = 0; b < kNB; ++b)
+#pragma unroll
+                for (int e = 0; e < 4; e += 2) {
+                    const _Float16 lo = (_Float16)dp[i][b][e], hi = (_Float16)dp[i][b][e + 1];
+                    DPs[L][(i * kNB + b) * 2 + e / 2][t] = (unsigned int)__builtin_bit_cast(unsigned short, lo) |
+                                                           ((unsigned int)__builtin_bit_cast(unsigned short, hi) << 16);
+                }
+    };
+    auto load_dp = [&](int L) {
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+            for (int b = 0; b < kNB; ++b)
+#pragma unroll
+                for (int e = 0; e < 4; e += 2) {
+                    const unsigned int w = DPs[L][(i * kNB + b) * 2 + e / 2][t];
+                    dp[i][b][e] = (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xffffu));
+                    dp[i][b][e + 1] = (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16));
+                }
     };
     // forward layers start from the bias: a = bias + sum_k h_k W_ck, the sum
     // accumulated onto it by the matrix core
@@ -229,7 +259,8 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
             for (int b = 0; b < kNB; ++b) acc[i][b] = mfma(af, bfr[b], acc[i][b]);
         }
         bf16x4 hv[RB][kNB];
-        fwd_epilogue(dp[0], hv, a.ht + (int64_t)kIn * kp);
+        fwd_epilogue(dp, hv, a.ht + (int64_t)kIn * kp);
+        store_dp(0);
         store_lds(hv);
         __syncthreads();
     }
@@ -239,7 +270,8 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
         product256();
         load_w(a.wb + kOffW3);  // next: layer 3
         bf16x4 hv[RB][kNB];
-        fwd_epilogue(dp[1], hv, a.ht + (int64_t)(kIn + kH) * kp);
+        fwd_epilogue(dp, hv, a.ht + (int64_t)(kIn + kH) * kp);
+        store_dp(1);
         __syncthreads();  // every wave has read h1
         store_lds(hv);
         __syncthreads();
@@ -250,7 +282,8 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
         product256();
         load_w(a.wt + kWt3);  // next: the g2 product
         bf16x4 hv[RB][kNB];
-        fwd_epilogue(dp[2], hv, a.ht + (int64_t)(kIn + 2 * kH) * kp);
+        fwd_epilogue(dp, hv, a.ht + (int64_t)(kIn + 2 * kH) * kp);
+        store_dp(2);
         __syncthreads();  // every wave has read h2
         store_lds(hv);
         __syncthreads();
@@ -333,7 +366,8 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
             for (int b = 0; b < kNB; ++b) acc[i][b] = mfma(af, bfr[b], acc[i][b]);
         }
         bf16x4 gv[RB][kNB];
-        bwd_epilogue(2, dp[2], gv);
+        load_dp(2);
+        bwd_epilogue(2, dp, gv);
         store_lds(gv);  // Hs (h3) was last read by layer 4, before the barrier above
         __syncthreads();
     }
@@ -343,7 +377,8 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
         product256();
         load_w(a.wt + kWt2);  // next: the g1 product
         bf16x4 gv[RB][kNB];
-        bwd_epilogue(1, dp[1], gv);
+        load_dp(1);
+        bwd_epilogue(1, dp, gv);
         __syncthreads();  // every wave has read g3
         store_lds(gv);
         __syncthreads();
@@ -354,7 +389,8 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
         product256();
 
         bf16x4 gv[RB][kNB];
-        bwd_epilogue(0, dp[0], gv);
+        load_dp(0);
+        bwd_epilogue(0, dp, gv);
     }
 }
 
@@ -664,8 +700,11 @@ void launch_train_step(const TrainArgs& a, float lr, int step, hipStream_t s)
     // rows padded to a multiple of 64 (the weight products' K step); the
     // padding rows have zero loss gradient
     const int64_t kp = ((int64_t)a.n + kWK - 1) / kWK * kWK;
-    const int blocks = (int)(kp / kTR);
-    hipLaunchKernelGGL(train_pass_kernel, dim3(blocks), dim3(kPT), 0, s, a);
+    // 64 rows per pass workgroup where that still gives every compute unit one
+    const bool wide = kp >= 64 * 256;
+    const int blocks = (int)(kp / (wide ? 64 : 32));
+    if (wide) hipLaunchKernelGGL(train_pass_kernel<64>, dim3(blocks), dim3(kPT), 0, s, a);
+    else hipLaunchKernelGGL(train_pass_kernel<32>, dim3(blocks), dim3(kPT), 0, s, a);
     const int slices = train_slices(a.n);
     const int kslice = (int)(((kp + slices - 1) / slices + kWK - 1) / kWK * kWK);
     const int quads = 3 * slices;

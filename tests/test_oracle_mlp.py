@@ -133,6 +133,34 @@ def test_matmul_bf16_within_float32_bound():
                   <= 2 * 2.0 ** -8 * (np.abs(A) @ np.abs(B)) + 1e-30)
 
 
+def test_f16_rounding_bitwise():
+    """The float16 rounding point of the emulation against the binary16
+    format written out: 11 significant bits, ties to even, subnormals in
+    steps of 2^-24, and the range GELU' takes."""
+    cases = {
+        1.0 + 2.0 ** -11: 1.0,                         # tie -> even (1.0)
+        1.0 + 3 * 2.0 ** -11: 1.0 + 2 * 2.0 ** -10,    # tie -> even (the larger)
+        1.0 + 2.0 ** -11 + 2.0 ** -20: 1.0 + 2.0 ** -10,  # above the tie
+        -1.128: -(1.0 + 131 * 2.0 ** -10),             # nearest of the grid of [1, 2)
+        3 * 2.0 ** -25: 2.0 ** -23,                    # subnormal tie (1.5 steps) -> even (2 steps)
+        2.0 ** -26: 0.0,                               # below half a subnormal step
+    }
+    for x, want in cases.items():
+        assert M.f16(np.float32(x)) == np.float32(want), x
+    # every value of [-0.2, 1.2]: the result lies on the binary16 grid of its
+    # binade and is the nearest grid point
+    xs = np.linspace(-0.2, 1.2, 20001, dtype=np.float32)
+    r = M.f16(xs).astype(np.float64)
+    for x, y in zip(xs.astype(np.float64), r):
+        if x == 0.0:
+            assert y == 0.0
+            continue
+        e = max(math.floor(math.log2(abs(x))), -14)
+        step = 2.0 ** (e - 10)
+        assert abs(y / step - round(y / step)) == 0.0
+        assert abs(y - x) <= step / 2
+
+
 def test_bf16_forward_and_gradient_close_to_fp64():
     p = _params(11)
     rng = np.random.default_rng(12)

@@ -539,14 +539,22 @@ __global__ __launch_bounds__(256) void train_transpose_kernel(TrainArgs a)
     }
 }
 
-__device__ __forceinline__ float adam_one(const TrainArgs& a, int i, float g, float lr, float c1, float c2)
+// One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; c1, c2 the bias corrections)
+__device__ __forceinline__ void adam_math(float w, float m, float v, float g, float lr, float c1, float c2, float& wn,
+                                          float& mn, float& vn)
 {
     const float b1 = 0.9f, b2 = 0.999f;
-    const float mi = b1 * a.am[i] + (1.f - b1) * g;
-    const float vi = b2 * a.av[i] + (1.f - b2) * g * g;
-    a.am[i] = mi;
-    a.av[i] = vi;
-    const float w = a.params[i] - lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+    mn = b1 * m + (1.f - b1) * g;
+    vn = b2 * v + (1.f - b2) * g * g;
+    wn = w - lr * (mn / c1) / (sqrtf(vn / c2) + 1e-8f);
+}
+
+__device__ __forceinline__ float adam_one(const TrainArgs& a, int i, float g, float lr, float c1, float c2)
+{
+    float w, m, v;
+    adam_math(a.params[i], a.am[i], a.av[i], g, lr, c1, c2, w, m, v);
+    a.am[i] = m;
+    a.av[i] = v;
     a.params[i] = w;
     a.wb[i] = to_bf16(w);
     return w;
@@ -576,7 +584,11 @@ __global__ __launch_bounds__(256) void train_update_kernel(TrainArgs a, int slic
         const int r = t >> 3, cq = t & 7;
         const int off = mat == 0 ? kOffW2 : kOffW3;
         const int i0 = off + (o0 + r) * kH + k0 + 4 * cq;
-        // every slice's load issued before the sum (in slice order)
+        // the Adam state and every slice's partial sums requested at once
+        // (the sum is taken in slice order)
+        const f32x4 w0 = *reinterpret_cast<const f32x4*>(a.params + i0);
+        const f32x4 m0 = *reinterpret_cast<const f32x4*>(a.am + i0);
+        const f32x4 v0 = *reinterpret_cast<const f32x4*>(a.av + i0);
         f32x4 p[kTrainSlices];
 #pragma unroll
         for (int s = 0; s < kTrainSlices; ++s)
@@ -588,8 +600,20 @@ __global__ __launch_bounds__(256) void train_update_kernel(TrainArgs a, int slic
             if (s < slices) g += p[s];
         if (a.grad) *reinterpret_cast<f32x4*>(a.grad + i0) = g;
         if (!(lr > 0.f)) return;
+        f32x4 wn, mn, vn;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) T[4 * cq + e][r] = to_bf16(adam_one(a, i0 + e, g[e], lr, c1, c2));
+        for (int e = 0; e < 4; ++e) {
+            float we, me, ve;
+            adam_math(w0[e], m0[e], v0[e], g[e], lr, c1, c2, we, me, ve);
+            wn[e] = we;
+            mn[e] = me;
+            vn[e] = ve;
+            T[4 * cq + e][r] = to_bf16(we);
+        }
+        *reinterpret_cast<f32x4*>(a.params + i0) = wn;
+        *reinterpret_cast<f32x4*>(a.am + i0) = mn;
+        *reinterpret_cast<f32x4*>(a.av + i0) = vn;
+        *reinterpret_cast<bf16x4*>(a.wb + i0) = bf16x4{to_bf16(wn[0]), to_bf16(wn[1]), to_bf16(wn[2]), to_bf16(wn[3])};
         __syncthreads();
         // W^T rows k0 + r, columns o0 + 4 cq .. + 3
         __bf16* WT = a.wt + (mat == 0 ? kWt2 : kWt3);

@@ -20,12 +20,22 @@ constexpr int kMlpParams = kH * kIn + kH + kH * kH + kH + kH * kH + kH + kOut * 
 //       at kWt2, W3^T at kWt3, W4^T [256][8] (columns 3..7 zero) at kWt4
 //   ht  layer inputs, feature-major bf16: h0 [8][kpad], h1, h2, h3 [256][kpad]
 //   gt  layer gradients, feature-major bf16: g1, g2, g3 [256][kpad], g4 [3][kpad]
-//   dbp bias-gradient sums per 32-row block, slot-major: slot s (kBiasGrads
-//       slots) of block b at dbp[s * (kpad / 32) + b]
-//   wpart weight-gradient sums per row slice, kWpartStride floats per slice
+//   dbp gradient sums per row block of the pass kernel (kPartSlots slots:
+//       the 771 biases, W1, W4), at part_index(slot, block, kpad / 32)
+//   wpart W2 / W3 gradient sums per row slice, kWpartStride floats per slice
 constexpr int kWt2 = 0, kWt3 = kH * kH, kWt4 = 2 * kH * kH, kWtElems = 2 * kH * kH + kH * 8;
 constexpr int kBiasGrads = 3 * kH + kOut;
-constexpr int kTrainSlices = 21;
+// per-block partial sums: the biases, then W1 (i-major: slot i * 256 + o for
+// W1[o][i]) and W4 (flat: c * 256 + k), stored in groups of 16 slots, one
+// 64-byte line per (group, block): slot s of block b at
+// ((s / 16) * nblk + b) * 16 + s % 16, nblk = kpad / 32
+constexpr int kPartSlots = kBiasGrads + kH * kIn + kOut * kH;
+constexpr int kPartGroups = (kPartSlots + 15) / 16;
+__host__ __device__ constexpr int64_t part_index(int slot, int64_t blk, int64_t nblk)
+{
+    return ((int64_t)(slot >> 4) * nblk + blk) * 16 + (slot & 15);
+}
+constexpr int kTrainSlices = 32;
 constexpr int kWpartStride = (kMlpParams + 63) / 64 * 64;  // floats per slice of wpart (16-byte aligned slices)
 
 struct TrainArgs {

@@ -93,7 +93,7 @@ void carve_trainer(Carver& c, Trainer& t, int64_t rows, int64_t se_rows)
     t.wt = c.take<__bf16>(kWtElems);
     t.ht = c.take<__bf16>((size_t)(kIn + 3 * kH) * t.kpad);
     t.gt = c.take<__bf16>((size_t)(3 * kH + kOut) * t.kpad);
-    t.dbp = c.take<float>((size_t)blocks * kBiasGrads);
+    t.dbp = c.take<float>((size_t)blocks * kPartGroups * 16);
     t.wpart = c.take<float>((size_t)kTrainSlices * kWpartStride);
     t.lpart = c.take<double>(kSeParts + 1);
 }

@@ -17,8 +17,9 @@
 //     layers' inputs h_{l-1} and gradients g_l transposed (feature-major,
 //     bfloat16) for the weight products, the per-row squared errors and the
 //     block's bias-gradient sums.
-//   kernel 2 (train_wgrad_kernel): dW_l = g_l^T h_{l-1} over the minibatch
-//     rows, as 128 x 128 output tiles over row slices (partial sums per slice).
+//   kernel 2 (train_wgrad_kernel): dW_l = g_l^T h_{l-1} of W2 and W3 over
+//     the minibatch rows, as 128 x 128 output tiles over row slices (partial
+//     sums per slice); the thin W1 and W4 are summed per row block by kernel 1.
 //   kernel 3 (train_update_kernel): per parameter, the slices' (weights) or
 //     blocks' (biases) partial sums added in fixed orders -- the gradient,
 //     deterministic -- then Adam and the bfloat16 copies of the new weights,
@@ -67,6 +68,16 @@ __device__ __forceinline__ void gelu_both(float x, float& g, float& dg)
 }
 
 __device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
+// eight bf16 at p, p + stride, ..., p + 7 stride (a column of a row-major
+// LDS array as a K-contiguous operand fragment)
+__device__ __forceinline__ bf16x8 gather8(const __bf16* p, int stride)
+{
+    bf16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = p[j * stride];
+    return v;
+}
 
 // four consecutive bf16 (8 bytes)
 __device__ __forceinline__ void st4(__bf16* p, float a, float b, float c, float d)
@@ -118,6 +129,7 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
     __shared__ __attribute__((aligned(16))) __bf16 Xs[TR][kXP];  // x, then g4, K padded to 32
     __shared__ float G4[TR][4];
     __shared__ float Dl[TR][4];
+    __shared__ __attribute__((aligned(16))) __bf16 Xf[16][TR + 8];  // x feature-major (rows 8..15 zero), for dW1
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63, lr = lane & 15, lg = lane >> 4;
     const int blk = blockIdx.x;
     const int r0 = blk * TR;
@@ -149,13 +161,14 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
         Xs[r][k] = to_bf16(v);
     }
     __syncthreads();
-    for (int i = t; i < kIn * TR; i += kPT) {
+    for (int i = t; i < 16 * TR; i += kPT) {
         const int k = i / TR, r = i % TR;
-        a.ht[(int64_t)k * kp + r0 + r] = Xs[r][k];  // h0^T
+        Xf[k][r] = Xs[r][k];                                       // zero for k >= 8
+        if (k < kIn) a.ht[(int64_t)k * kp + r0 + r] = Xs[r][k];  // h0^T
     }
 
     f32x4 acc[RB][kNB];
-    __shared__ unsigned int DPs[3][RB * kNB * 2][kPT];  // GELU'(a_l), float16 pairs
+    __shared__ __attribute__((aligned(16))) unsigned int DPs[3][RB * kNB * 2][kPT];  // GELU'(a_l), float16 pairs
     float dp[RB][kNB][4];  // GELU'(a_l) of the layer at hand, this lane's elements
     auto zero_acc = [&]() {
 #pragma unroll
@@ -324,7 +337,7 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
     if (t < kOut) {
         float s = 0.f;
         for (int r = 0; r < TR; ++r) s += G4[r][t];
-        a.dbp[(int64_t)(3 * kH + t) * nblk + blk] = s;
+        a.dbp[part_index(3 * kH + t, blk, nblk)] = s;
     }
     // bf16(g4) as the K-padded operand of the first data product
     for (int i = t; i < TR * 32; i += kPT) {
@@ -332,6 +345,28 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
         Xs[r][k] = to_bf16(k < kOut ? G4[r][k] : 0.f);
     }
     __syncthreads();
+    // this block's part of dW4 = g4^T h3 (3 x 256, K = the block's rows):
+    // A = bf16(g4) columns of Xs, B = h3 columns of Hs (the wave's own
+    // columns, which only it overwrites later), both gathered K-contiguous
+    {
+        f32x4 w4[kNB];
+#pragma unroll
+        for (int b = 0; b < kNB; ++b) w4[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k0 = 0; k0 < TR; k0 += 32) {
+            const bf16x8 af = gather8(&Xs[k0 + 8 * lg][lr], kXP);
+#pragma unroll
+            for (int b = 0; b < kNB; ++b)
+                w4[b] = mfma(af, gather8(&Hs[k0 + 8 * lg][c0 + 16 * b + lr], kTP), w4[b]);
+        }
+        if (lg == 0) {  // rows c = e < 3 of the product
+#pragma unroll
+            for (int b = 0; b < kNB; ++b)
+#pragma unroll
+                for (int e = 0; e < kOut; ++e)
+                    a.dbp[part_index(kBiasGrads + kH * kIn + e * kH + c0 + 16 * b + lr, blk, nblk)] = w4[b][e];
+        }
+    }
 
     // backward epilogue of hidden layer L (2, 1, 0): g = acc * GELU'(a_L);
     // g^T to global and g to gp (bfloat16), the block's bias sums (FP32 g).
@@ -350,7 +385,7 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
                 grow[4 * i] = gp[i][b];
             }
             const float s = block_colsum<RB>(cs);
-            if (lg == 0) a.dbp[(int64_t)(L * kH + c) * nblk + blk] = s;
+            if (lg == 0) a.dbp[part_index(L * kH + c, blk, nblk)] = s;
         }
     };
     // ---- g3 = (g4 W4) * GELU'(a3): K = 3 padded to 32, B from W4^T [256][8]
@@ -391,13 +426,39 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
         bf16x4 gv[RB][kNB];
         load_dp(0);
         bwd_epilogue(0, dp, gv);
+        // this block's part of dW1 = g1^T h0 (256 x 8, K = the block's rows),
+        // as dW1^T = h0^T g1 with both operands feature-major in LDS: x in
+        // Xf, g1 in the GELU' space (free now)
+        __bf16(*Gf)[TR + 8] = reinterpret_cast<__bf16(*)[TR + 8]>(&DPs[0][0][0]);
+        __syncthreads();  // every wave is done with GELU'
+#pragma unroll
+        for (int b = 0; b < kNB; ++b)
+#pragma unroll
+            for (int i = 0; i < RB; ++i) *reinterpret_cast<bf16x4*>(&Gf[c0 + 16 * b + lr][16 * i + 4 * lg]) = gv[i][b];
+        __syncthreads();
+        f32x4 w1[kNB];
+#pragma unroll
+        for (int b = 0; b < kNB; ++b) w1[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k0 = 0; k0 < TR; k0 += 32) {
+            const bf16x8 af = ld8(&Xf[lr][k0 + 8 * lg]);
+#pragma unroll
+            for (int b = 0; b < kNB; ++b) w1[b] = mfma(af, ld8(&Gf[c0 + 16 * b + lr][k0 + 8 * lg]), w1[b]);
+        }
+        if (lg < 2) {  // rows i = 4 lg + e < 8 of dW1^T
+#pragma unroll
+            for (int b = 0; b < kNB; ++b)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    a.dbp[part_index(kBiasGrads + (4 * lg + e) * kH + c0 + 16 * b + lr, blk, nblk)] = w1[b][e];
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // Kernel 2.  dW = g^T h over row slice s: C[m][n] = sum_k Gt[m][k] Ht[n][k]
 // (both feature-major, K = rows contiguous).  Workgroup: one 128 x 128 output
-// tile of one matrix (M, N bounds for the thin W1 and W4), 4 waves of 64 x 64
+// tile of W2 or W3, 4 waves of 64 x 64
 // (4 x 4 blocks of 16 x 16).  K advances 64 rows a step through two LDS
 // buffers (one barrier a step); each thread's global loads run three steps
 // ahead of their LDS stores, so the L2 / HBM latency is spread over three
@@ -416,35 +477,28 @@ struct WStage {
 // Workgroup L of the (1-D) grid: quads of four tiles, quad p = (L % 8) +
 // 8 ((L / 8) / 4), tile (L / 8) % 4 of it, so that a quad's workgroups share
 // an XCD (workgroups go to the eight XCDs in turn) and its second read of
-// each operand row is served by that XCD's L2.  Quad p: slice p / 3 of W2
-// (p % 3 = 0), of W3 (1), or of the thin W1 and W4 (2: two tiles each).
+// each operand row is served by that XCD's L2.  Quad p: slice p / 2 of W2
+// (p even) or W3 (p odd); the thin W1 and W4 are summed per row block by
+// the pass kernel.
 __global__ __launch_bounds__(256) void train_wgrad_kernel(TrainArgs a, int krows, int kslice, int slices)
 {
     __shared__ __attribute__((aligned(16))) __bf16 As[2][128][kWP];
     __shared__ __attribute__((aligned(16))) __bf16 Bs[2][128][kWP];
     const int L = blockIdx.x, quad = (L & 7) + 8 * ((L >> 3) >> 2), u = (L >> 3) & 3;
-    if (quad >= 3 * slices) return;  // whole workgroup
-    const int s = quad / 3, kind = quad % 3;
-    struct { int mat, m0, n0; } tl;
-    if (kind < 2) tl = {1 + kind, 128 * (u >> 1), 128 * (u & 1)};
-    else if (u < 2) tl = {0, 128 * u, 0};
-    else tl = {3, 0, 128 * (u - 2)};
+    if (quad >= 2 * slices) return;  // whole workgroup
+    const int s = quad >> 1;
+    struct { int mat, m0, n0; } tl = {1 + (quad & 1), 128 * (u >> 1), 128 * (u & 1)};
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63, lr = lane & 15, lg = lane >> 4;
     const int64_t kp = a.kpad;
-    // operand matrices: rows of Gt (outputs) and of Ht (inputs), their counts and the output
-    int M, N, gOff, hOff, wOff;
-    if (tl.mat == 0) { M = kH; N = kIn; gOff = 0; hOff = 0; wOff = 0; }
-    else if (tl.mat == 1) { M = kH; N = kH; gOff = kH; hOff = kIn; wOff = kOffW2; }
-    else if (tl.mat == 2) { M = kH; N = kH; gOff = 2 * kH; hOff = kIn + kH; wOff = kOffW3; }
-    else { M = kOut; N = kH; gOff = 3 * kH; hOff = kIn + 2 * kH; wOff = kOffW4; }
+    // operand matrices: rows of Gt (the layer's gradients) and of Ht (its inputs), and the output
+    const int gOff = tl.mat == 1 ? kH : 2 * kH, hOff = tl.mat == 1 ? kIn : kIn + kH;
+    const int wOff = tl.mat == 1 ? kOffW2 : kOffW3;
     // krows and kslice are multiples of kWK: every step is whole
     const int kb = s * kslice, ke = min(krows, kb + kslice);  // this minibatch's rows only
     const int nsteps = kb < ke ? (ke - kb) / kWK : 0;
-    // rows past a thin matrix's bound read its last row instead: they only
-    // reach outputs past the bound, which are not written
     const int sr = t >> 1, sk = 32 * (t & 1);
-    const __bf16* G = a.gt + (int64_t)(gOff + min(tl.m0 + sr, M - 1)) * kp + kb + sk;
-    const __bf16* H = a.ht + (int64_t)(hOff + min(tl.n0 + sr, N - 1)) * kp + kb + sk;
+    const __bf16* G = a.gt + (int64_t)(gOff + tl.m0 + sr) * kp + kb + sk;
+    const __bf16* H = a.ht + (int64_t)(hOff + tl.n0 + sr) * kp + kb + sk;
     auto load = [&](int j, WStage& r) {
         if (j < nsteps) {
 #pragma unroll
@@ -506,7 +560,7 @@ __global__ __launch_bounds__(256) void train_wgrad_kernel(TrainArgs a, int krows
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int m = tl.m0 + wm + 16 * i + 4 * lg + e, nn = tl.n0 + wn + 16 * j + lr;
-                if (m < M && nn < N) out[(int64_t)m * N + nn] = acc[i][j][e];
+                out[(int64_t)m * kH + nn] = acc[i][j][e];
             }
 }
 
@@ -561,16 +615,15 @@ __device__ __forceinline__ float adam_one(const TrainArgs& a, int i, float g, fl
 }
 
 // Workgroups of the update: 128 tiles of 32 x 32 weights of W2 and W3
-// (their transposed bfloat16 copies written through LDS), then the 2816
-// weights of W1 and W4 one per thread, then the 771 biases one per wave.
+// (their transposed bfloat16 copies written through LDS), then one per group
+// of 16 slots of the block sums (the 771 biases, the 2816 weights of W1 and
+// W4).
 constexpr int kUpdTiles = 2 * (kH / 32) * (kH / 32);
-constexpr int kUpdThin = (kH * kIn + kOut * kH + 255) / 256;
-constexpr int kUpdBias = (kBiasGrads + 3) / 4;
-constexpr int kUpdBlocks = kUpdTiles + kUpdThin + kUpdBias;
+constexpr int kUpdBlocks = kUpdTiles + kPartGroups;
 
-// Parameter i's gradient: weights, the slices' sums in slice order; biases,
-// lane l sums blocks l, l + 64, ... in order and the lanes are added by a
-// fixed butterfly.  Written to grad if given; with lr > 0 the Adam step
+// Parameter i's gradient: W2 and W3, the slices' sums in slice order; the
+// biases, W1 and W4 (block sums of the pass kernel), lane l sums blocks l,
+// l + 64, ... in order and the lanes are added by a fixed butterfly.  Written to grad if given; with lr > 0 the Adam step
 // (bias corrections c1, c2 from the host) and the bfloat16 copies.
 __global__ __launch_bounds__(256) void train_update_kernel(TrainArgs a, int slices, int blocks, float lr, float c1,
                                                            float c2)
@@ -621,47 +674,46 @@ __global__ __launch_bounds__(256) void train_update_kernel(TrainArgs a, int slic
         *reinterpret_cast<bf16x4*>(WT + (k0 + r) * kH + o0 + 4 * cq) = v;
         return;
     }
-    if (bx < kUpdTiles + kUpdThin) {
-        const int j = (bx - kUpdTiles) * 256 + t;
-        if (j >= kH * kIn + kOut * kH) return;
-        const int i = j < kH * kIn ? j : kOffW4 + (j - kH * kIn);
-        float p[kTrainSlices];
-#pragma unroll
-        for (int s = 0; s < kTrainSlices; ++s) p[s] = s < slices ? a.wpart[(int64_t)s * kWpartStride + i] : 0.f;
-        float g = p[0];
-#pragma unroll
-        for (int s = 1; s < kTrainSlices; ++s)
-            if (s < slices) g += p[s];
-        if (a.grad) a.grad[i] = g;
-        if (!(lr > 0.f)) return;
-        const float w = adam_one(a, i, g, lr, c1, c2);
-        if (i >= kOffW4) {  // W4^T [256][8]: element (k, c) = W4[c][k]
-            const int c = (i - kOffW4) / kH, k = (i - kOffW4) % kH;
-            a.wt[kWt4 + k * 8 + c] = to_bf16(w);
-        }
-        return;
-    }
-    const int slot = (bx - kUpdTiles - kUpdThin) * 4 + (t >> 6), lane = t & 63;
-    if (slot >= kBiasGrads) return;  // whole wave
+    // group G of 16 slots: thread (wave v, lane l) sums slot 16 G + l % 16 over
+    // blocks q, q + 16, ... (q = 4 v + l / 16; each 16-lane quarter reads
+    // whole 64-byte lines), the quarters are added by a fixed butterfly, the
+    // four waves in order through LDS
+    __shared__ float red[4][16];
+    const int G = bx - kUpdTiles, lane = t & 63, v = t >> 6, j = lane & 15, q = 4 * v + (lane >> 4);
+    const int64_t nblk = a.kpad / 32;
     float g = 0.f;
-    for (int b0 = lane; b0 < blocks; b0 += 8 * 64) {  // eight loads in flight, added in block order
-        float p[8];
+    for (int b0 = q; b0 < blocks; b0 += 32 * 16) {  // 32 loads in flight, added in block order
+        float p[32];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int b = b0 + 64 * u;
-            p[u] = b < blocks ? a.dbp[(int64_t)slot * (a.kpad / 32) + b] : 0.f;
+        for (int u = 0; u < 32; ++u) {
+            const int b = b0 + 16 * u;
+            p[u] = b < blocks ? a.dbp[part_index(16 * G + j, b, nblk)] : 0.f;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (b0 + 64 * u < blocks) g += p[u];
+        for (int u = 0; u < 32; ++u)
+            if (b0 + 16 * u < blocks) g += p[u];
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) g += __shfl_xor(g, off, 64);
-    if (lane != 0) return;
-    const int i = slot < 3 * kH ? (slot < kH ? kOffB1 + slot : slot < 2 * kH ? kOffB2 + slot - kH : kOffB3 + slot - 2 * kH)
-                                : kOffB4 + slot - 3 * kH;
+    g += __shfl_xor(g, 16, 64);
+    g += __shfl_xor(g, 32, 64);
+    if (lane < 16) red[v][j] = g;
+    __syncthreads();
+    if (t >= 16) return;
+    const int slot = 16 * G + t;
+    if (slot >= kPartSlots) return;
+    g = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+    // slot -> parameter: b1, b2, b3, b4, then W1 (i-major) and W4 (flat)
+    const int w = slot - kBiasGrads;
+    const int i = slot < 3 * kH      ? (slot < kH ? kOffB1 + slot : slot < 2 * kH ? kOffB2 + slot - kH : kOffB3 + slot - 2 * kH)
+                  : slot < kBiasGrads ? kOffB4 + slot - 3 * kH
+                  : w < kH * kIn      ? (w % kH) * kIn + w / kH
+                                      : kOffW4 + (w - kH * kIn);
     if (a.grad) a.grad[i] = g;
-    if (lr > 0.f) adam_one(a, i, g, lr, c1, c2);
+    if (!(lr > 0.f)) return;
+    const float wn = adam_one(a, i, g, lr, c1, c2);
+    if (i >= kOffW4 && i < kOffB4) {  // W4^T [256][8]: element (k, c) = W4[c][k]
+        const int c = (i - kOffW4) / kH, k = (i - kOffW4) % kH;
+        a.wt[kWt4 + k * 8 + c] = to_bf16(wn);
+    }
 }
 
 // bfloat16 copy of the current parameters (before a pass that follows an
@@ -708,8 +760,8 @@ void launch_se_sum(const float* se, int64_t n, double* part, hipStream_t s)
 int train_slices(int64_t rows)
 {
     const int64_t kp = (rows + kWK - 1) / kWK * kWK;
-    // about 256 rows per slice or more, at most kTrainSlices (12 output
-    // tiles x 21 slices: about one workgroup per compute unit)
+    // about 256 rows per slice or more, at most kTrainSlices (8 output
+    // tiles x 32 slices: one workgroup per compute unit)
     return (int)std::max<int64_t>(1, std::min<int64_t>(kTrainSlices, kp / 256));
 }
 
@@ -731,7 +783,7 @@ void launch_train_step(const TrainArgs& a, float lr, int step, hipStream_t s)
     else hipLaunchKernelGGL(train_pass_kernel<32>, dim3(blocks), dim3(kPT), 0, s, a);
     const int slices = train_slices(a.n);
     const int kslice = (int)(((kp + slices - 1) / slices + kWK - 1) / kWK * kWK);
-    const int quads = 3 * slices;
+    const int quads = 2 * slices;
     hipLaunchKernelGGL(train_wgrad_kernel, dim3(32 * ((quads + 7) / 8)), dim3(256), 0, s, a, (int)kp, kslice, slices);
     float c1 = 1.f, c2 = 1.f;
     if (lr > 0.f) {

@@ -68,6 +68,27 @@ def test_gradients_match_bf16_oracle(n):
         assert el <= 1e-3, (name, el)
 
 
+def test_gradients_match_bf16_oracle_wide_blocks():
+    """A minibatch large enough for the pass kernel's 64-row workgroups
+    (16448 rows: 257 of them, the last padded to the 64-row K step), whose
+    per-block sums carry the bias, W1 and W4 gradients: element by element
+    against the emulating oracle, as at small sizes."""
+    n = 16448
+    p = _params(9)
+    rng = np.random.default_rng(900)
+    x = rng.uniform(-1, 1, (n, 8)).astype(np.float32)
+    y = _smooth_targets(x)
+    g, loss = A.mlp_gradients(p, x, y)
+    lo, go = M.loss_grad_bf16(p, x, y)
+    assert abs(loss - lo) <= 1e-4 * lo
+    for name, (a, b) in M.offsets().items():
+        rel = np.linalg.norm(g[a:b] - go[a:b]) / np.linalg.norm(go[a:b])
+        el = np.max(np.abs(g[a:b] - go[a:b])) / np.max(np.abs(go[a:b]))
+        print(f"gradient {name}: relative norm error {rel:.2e}, largest element error {el:.2e}", flush=True)
+        assert rel <= 1e-3, (name, rel)
+        assert el <= 1e-3, (name, el)
+
+
 def test_training_tracks_bf16_oracle():
     rng = np.random.default_rng(7)
     x = rng.uniform(-1, 1, (1000, 8)).astype(np.float32)

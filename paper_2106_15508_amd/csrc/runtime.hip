@@ -423,115 +423,153 @@ int abcsmc_round(abcsmc_ctx* x, abcsmc_round_info* info)
         const int rc = surrogate_batches(x, pa, dst, nxt, hc, base, batches, ms_k_propose);
         if (rc) return rc;
     }
-    while (!screened) {
-        int64_t B;
-        if (r == 0) {
-            B = std::min<int64_t>(cap, (int64_t)N - (int64_t)hc.accepted);
-        } else if (c.batch > 0) {
-            B = c.batch;
-        } else {
-            const double need = (double)(N - (int64_t)hc.accepted);
-            const double rate = x->last_rate > 1e-4 ? x->last_rate : 1e-4;
-            B = (int64_t)std::ceil(need / rate * 1.1) + 2048;
-            B = (B + kBlock - 1) / kBlock * kBlock;
-            // stage 1 has no measured acceptance rate yet: its first batch is
-            // capped (a batch sized by the 0.5 guess simulated twice the
-            // proposals needed at C2); later batches use the rate measured
-            if (r == 1 && base == 0 && x->first_batch > 0 && B > x->first_batch) B = x->first_batch;
-            if (B > cap) B = cap;
-        }
-        if (base + B > c.max_proposals) B = c.max_proposals - base;
-        if (B <= 0) return fail(&x->err, ABCSMC_EBUDGET, "stage exhausted its proposal budget");
-        pa.base = (uint32_t)base;
-        pa.count = (uint32_t)B;
-        HIPCHK(x, hipEventRecord(x->ev[5], s));
-        launch_propose(pa, r == 0, s);
-        HIPCHK(x, hipGetLastError());
-        HIPCHK(x, hipEventRecord(x->ev[6], s));
-        ca.base = pa.base;
-        ca.count = pa.count;
-        launch_compact(ca, s);
-        HIPCHK(x, hipGetLastError());
-        HIPCHK(x, hipMemcpyAsync(&hc, ctr, sizeof hc, hipMemcpyDeviceToHost, s));
-        HIPCHK(x, hipStreamSynchronize(s));
-        ms_k_propose += elapsed(x->ev[5], x->ev[6]);
-        base += B;
-        ++batches;
-        if (mcmc && r > 0 && x->mcmc_tunes < c.mcmc_tune) {
-            // eqs. 14-15 over this batch: A = accepted / valid proposals
-            const int64_t acc_b = (int64_t)(hc.accepted - prev_acc);
-            const int64_t valid_b = B - (int64_t)(hc.invalid - prev_inv);
-            x->mcmc_nacc += acc_b;
-            const double A = valid_b > 0 ? (double)acc_b / (double)valid_b : 0.0;
-            x->mcmc_s = x->mcmc_s * (1.0 + (A - 0.234) / ((1.0 - 0.234) * ((double)x->mcmc_nacc + 1.0)));
-            x->mcmc_tunes += 1;
-            pa.s_fixed = x->mcmc_s;
-        }
-        prev_acc = hc.accepted;
-        prev_inv = hc.invalid;
-        if (hc.accepted >= (unsigned long long)N) break;
-        if (r > 0 && base > 0) x->last_rate = (double)hc.accepted / (double)base;
-    }
-    if (r > 0) x->last_rate = (double)N / (double)hc.proposals;
-    HIPCHK(x, hipEventRecord(x->ev[2], s));
+    // A first batch that will all but surely reach N acceptances (stage 0,
+    // where every valid proposal is accepted, and stages >= 2, sized from the
+    // measured rate with a margin) is not read back on its own: the stage
+    // goes straight on to its weights and tolerance, and the batch counters
+    // come back with them in one host wait.  A batch that falls short after
+    // all is completed by further batches, and the weights and tolerance are
+    // formed again (every result is that of the batch-by-batch loop).
+    bool spec_ok = !screened && !mcmc && !x->sur && r != 1;
+    int64_t pending = 0;  // size of a batch whose counters are not yet read
     const bool weighted = r > 0 && !(c.flags & ABCSMC_F_SKIP_WEIGHTS);
-    if (!weighted) {
-        launch_uniform_weights(dst.W, dst.logw, N, s);
-    } else {
-        WeightArgs wa{};
-        wa.u = dst.u;
-        wa.sigma = dst.sigma;
-        wa.cols = x->at<double>(x->L.cols);
-        wa.N = N;
-        wa.chunks = weight_window_chunks(N);
-        wa.cols_per_chunk = weight_cols_per_chunk(N);
-        wa.win = x->at<int2>(x->L.win);
-        wa.terms = &ctr->terms;
-        wa.window_terms = &ctr->window_terms;
-        wa.M = &ctr->survivors;
-        wa.partial = x->at<double>(x->L.wpart);
-        wa.logw = dst.logw;
-        wa.rowkeys = x->at<unsigned long long>(x->L.rowkeys);
-        wa.colkeys = x->at<unsigned long long>(x->L.colkeys);
-        wa.scols = x->at<double>(x->L.scols);
-        wa.skey = x->at<double>(x->L.skey);
-        wa.dimpart = x->at<double>(x->L.dimpart);
-        wa.dstar = x->at<int32_t>(x->L.dstar);
-        wa.npad = sort_padded_size((size_t)N);
-        wa.parent = dst.parent;
-        wa.u_prev = prev.u;
-        wa.q_prev = x->at<uint64_t>(x->L.q);
-        wa.cdf = x->at<uint64_t>(x->L.cdf);
-        wa.n_prev = N;
-        wa.rwin = x->at<double>(x->L.rwin);
-        wa.tab = x->at<double>(x->L.wtab);
-        weight_exp_constants(wa.ex);
-        launch_weights_window(wa, s);
-        HIPCHK(x, hipGetLastError());
-        HIPCHK(x, hipEventRecord(x->ev[7], s));
-        launch_weights_sum(wa, s);
-        HIPCHK(x, hipGetLastError());
-        HIPCHK(x, hipEventRecord(x->ev[8], s));
-        launch_weights_finalize(wa, s);
-        HIPCHK(x, hipGetLastError());
-        if (screened) {
-            const int rc = surrogate_weights(x, dst, nxt);
-            if (rc) return rc;
-        }
-        NormArgs na{dst.logw, dst.W, N, x->scratch(), scal + 1};
-        launch_normalise(na, s);
-    }
-    HIPCHK(x, hipGetLastError());
-    HIPCHK(x, hipEventRecord(x->ev[3], s));
-    SelectArgs sa{dst.d, N, c.surv_ratio, x->scratch(), scal + 0};
-    launch_select(sa, s);
-    HIPCHK(x, hipGetLastError());
-    HIPCHK(x, hipEventRecord(x->ev[4], s));
     double hs[2] = {0, 0};
     unsigned long long hterms[2] = {0, 0};  // terms, window_terms (adjacent counters)
-    HIPCHK(x, hipMemcpyAsync(hs, scal, sizeof hs, hipMemcpyDeviceToHost, s));
-    HIPCHK(x, hipMemcpyAsync(hterms, &ctr->terms, sizeof hterms, hipMemcpyDeviceToHost, s));
-    HIPCHK(x, hipStreamSynchronize(s));
+    for (;;) {
+        while (!screened) {
+            int64_t B;
+            bool sure = false;  // the batch is sized to reach N acceptances
+            if (r == 0) {
+                B = std::min<int64_t>(cap, (int64_t)N - (int64_t)hc.accepted);
+                sure = B == (int64_t)N - (int64_t)hc.accepted;
+            } else if (c.batch > 0) {
+                B = c.batch;
+            } else {
+                const double need = (double)(N - (int64_t)hc.accepted);
+                const double rate = x->last_rate > 1e-4 ? x->last_rate : 1e-4;
+                B = (int64_t)std::ceil(need / rate * 1.1) + 2048;
+                B = (B + kBlock - 1) / kBlock * kBlock;
+                sure = B <= cap;
+                // stage 1 has no measured acceptance rate yet: its first batch is
+                // capped (a batch sized by the 0.5 guess simulated twice the
+                // proposals needed at C2); later batches use the rate measured
+                if (r == 1 && base == 0 && x->first_batch > 0 && B > x->first_batch) B = x->first_batch;
+                if (B > cap) B = cap;
+            }
+            if (base + B > c.max_proposals) {
+                B = c.max_proposals - base;
+                sure = false;
+            }
+            if (B <= 0) return fail(&x->err, ABCSMC_EBUDGET, "stage exhausted its proposal budget");
+            pa.base = (uint32_t)base;
+            pa.count = (uint32_t)B;
+            HIPCHK(x, hipEventRecord(x->ev[5], s));
+            launch_propose(pa, r == 0, s);
+            HIPCHK(x, hipGetLastError());
+            HIPCHK(x, hipEventRecord(x->ev[6], s));
+            ca.base = pa.base;
+            ca.count = pa.count;
+            launch_compact(ca, s);
+            HIPCHK(x, hipGetLastError());
+            if (spec_ok && sure && batches == 0) {
+                pending = B;  // read back with the tolerance at the end of the stage
+                break;
+            }
+            HIPCHK(x, hipMemcpyAsync(&hc, ctr, sizeof hc, hipMemcpyDeviceToHost, s));
+            HIPCHK(x, hipStreamSynchronize(s));
+            ms_k_propose += elapsed(x->ev[5], x->ev[6]);
+            base += B;
+            ++batches;
+            if (mcmc && r > 0 && x->mcmc_tunes < c.mcmc_tune) {
+                // eqs. 14-15 over this batch: A = accepted / valid proposals
+                const int64_t acc_b = (int64_t)(hc.accepted - prev_acc);
+                const int64_t valid_b = B - (int64_t)(hc.invalid - prev_inv);
+                x->mcmc_nacc += acc_b;
+                const double A = valid_b > 0 ? (double)acc_b / (double)valid_b : 0.0;
+                x->mcmc_s = x->mcmc_s * (1.0 + (A - 0.234) / ((1.0 - 0.234) * ((double)x->mcmc_nacc + 1.0)));
+                x->mcmc_tunes += 1;
+                pa.s_fixed = x->mcmc_s;
+            }
+            prev_acc = hc.accepted;
+            prev_inv = hc.invalid;
+            if (hc.accepted >= (unsigned long long)N) break;
+            if (r > 0 && base > 0) x->last_rate = (double)hc.accepted / (double)base;
+        }
+        HIPCHK(x, hipEventRecord(x->ev[2], s));
+        if (!weighted) {
+            launch_uniform_weights(dst.W, dst.logw, N, s);
+        } else {
+            WeightArgs wa{};
+            wa.u = dst.u;
+            wa.sigma = dst.sigma;
+            wa.cols = x->at<double>(x->L.cols);
+            wa.N = N;
+            wa.chunks = weight_window_chunks(N);
+            wa.cols_per_chunk = weight_cols_per_chunk(N);
+            wa.win = x->at<int2>(x->L.win);
+            wa.terms = &ctr->terms;
+            wa.window_terms = &ctr->window_terms;
+            wa.M = &ctr->survivors;
+            wa.partial = x->at<double>(x->L.wpart);
+            wa.logw = dst.logw;
+            wa.rowkeys = x->at<unsigned long long>(x->L.rowkeys);
+            wa.colkeys = x->at<unsigned long long>(x->L.colkeys);
+            wa.scols = x->at<double>(x->L.scols);
+            wa.skey = x->at<double>(x->L.skey);
+            wa.dimpart = x->at<double>(x->L.dimpart);
+            wa.dstar = x->at<int32_t>(x->L.dstar);
+            wa.npad = sort_padded_size((size_t)N);
+            wa.parent = dst.parent;
+            wa.u_prev = prev.u;
+            wa.q_prev = x->at<uint64_t>(x->L.q);
+            wa.cdf = x->at<uint64_t>(x->L.cdf);
+            wa.n_prev = N;
+            wa.rwin = x->at<double>(x->L.rwin);
+            wa.tab = x->at<double>(x->L.wtab);
+            weight_exp_constants(wa.ex);
+            launch_weights_window(wa, s);
+            HIPCHK(x, hipGetLastError());
+            HIPCHK(x, hipEventRecord(x->ev[7], s));
+            launch_weights_sum(wa, s);
+            HIPCHK(x, hipGetLastError());
+            HIPCHK(x, hipEventRecord(x->ev[8], s));
+            launch_weights_finalize(wa, s);
+            HIPCHK(x, hipGetLastError());
+            if (screened) {
+                const int rc = surrogate_weights(x, dst, nxt);
+                if (rc) return rc;
+            }
+            NormArgs na{dst.logw, dst.W, N, x->scratch(), scal + 1};
+            launch_normalise(na, s);
+        }
+        HIPCHK(x, hipGetLastError());
+        HIPCHK(x, hipEventRecord(x->ev[3], s));
+        SelectArgs sa{dst.d, N, c.surv_ratio, x->scratch(), scal + 0};
+        launch_select(sa, s);
+        HIPCHK(x, hipGetLastError());
+        HIPCHK(x, hipEventRecord(x->ev[4], s));
+        HIPCHK(x, hipMemcpyAsync(hs, scal, sizeof hs, hipMemcpyDeviceToHost, s));
+        HIPCHK(x, hipMemcpyAsync(hterms, &ctr->terms, sizeof hterms, hipMemcpyDeviceToHost, s));
+        if (pending) HIPCHK(x, hipMemcpyAsync(&hc, ctr, sizeof hc, hipMemcpyDeviceToHost, s));
+        HIPCHK(x, hipStreamSynchronize(s));
+        if (pending) {
+            ms_k_propose += elapsed(x->ev[5], x->ev[6]);
+            base += pending;
+            ++batches;
+            pending = 0;
+            prev_acc = hc.accepted;
+            prev_inv = hc.invalid;
+            if (hc.accepted < (unsigned long long)N) {
+                // short of N after all: the remaining batches, then the weights again
+                if (r > 0) x->last_rate = (double)hc.accepted / (double)base;
+                spec_ok = false;
+                HIPCHK(x, hipMemsetAsync(&ctr->terms, 0, 2 * sizeof(unsigned long long), s));
+                continue;
+            }
+        }
+        break;
+    }  // stage passes
+    if (r > 0) x->last_rate = (double)N / (double)hc.proposals;
 
     // commit the stage
     x->cur = nxt;

@@ -116,6 +116,28 @@ def test_batch_size_does_not_change_results(oracle, batch):
         assert np.array_equal(_bits(a[i]["W"]), _bits(b[i]["W"]))
 
 
+def test_short_first_batch_completed_and_weights_redone(oracle):
+    """A later stage's first batch is sized from the previous stage's
+    acceptance rate and its counters come back only with the tolerance; when
+    the replayed tolerance of stage 2 drops far below the one stage 1 accepted
+    against, that batch falls short of N, the stage runs further batches and
+    forms its weights and tolerance again.  Every stage equals the oracle's
+    run under the same schedule."""
+    base = W.C1.with_(n_rounds=4, seed=5)
+    obs = oracle.observations(base)
+    pilot = oracle.run(base.with_(n_rounds=2), obs)
+    d1 = np.sort(pilot.dist[1])
+    sched = (float(pilot.eps_next[0]), float(d1[len(d1) // 50]))
+    wl = base.with_(eps_schedule=sched)
+    ref = oracle.run(wl, obs)
+    assert ref.rc == 0
+    infos, pops = _gpu_run(wl, obs, wl.n_rounds)
+    assert infos[2]["batches"] >= 2, infos[2]
+    _compare_run(oracle, wl, ref, infos, pops, wl.n_rounds)
+    # the terms counted are those of the one weight pass that stands
+    assert infos[2]["weight_terms"] <= wl.n_particles * infos[2]["survivors"]
+
+
 def test_early_exit_keeps_acceptances(oracle):
     wl = W.tiny(n_rounds=3)
     obs = oracle.observations(wl)

@@ -21,14 +21,16 @@ constexpr int kMlpParams = kH * kIn + kH + kH * kH + kH + kH * kH + kH + kOut * 
 //   ht  layer inputs, feature-major bf16: h0 [8][kpad], h1, h2, h3 [256][kpad]
 //   gt  layer gradients, feature-major bf16: g1, g2, g3 [256][kpad], g4 [3][kpad]
 //   dbp gradient sums per row block of the pass kernel (kPartSlots slots:
-//       the 771 biases, W1, W4), at part_index(slot, block, kpad / 32)
+//       the 771 biases, W1, W4), at part_index(slot, block, kpad / 32); a
+//       row block is 32 rows, or 64 for minibatches of 16384 rows or more
+//       (then only the first half of each group's blocks is written)
 //   wpart W2 / W3 gradient sums per row slice, kWpartStride floats per slice
 constexpr int kWt2 = 0, kWt3 = kH * kH, kWt4 = 2 * kH * kH, kWtElems = 2 * kH * kH + kH * 8;
 constexpr int kBiasGrads = 3 * kH + kOut;
 // per-block partial sums: the biases, then W1 (i-major: slot i * 256 + o for
 // W1[o][i]) and W4 (flat: c * 256 + k), stored in groups of 16 slots, one
 // 64-byte line per (group, block): slot s of block b at
-// ((s / 16) * nblk + b) * 16 + s % 16, nblk = kpad / 32
+// ((s / 16) * nblk + b) * 16 + s % 16, nblk = kpad / 32 (room for 32-row blocks)
 constexpr int kPartSlots = kBiasGrads + kH * kIn + kOut * kH;
 constexpr int kPartGroups = (kPartSlots + 15) / 16;
 __host__ __device__ constexpr int64_t part_index(int slot, int64_t blk, int64_t nblk)

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(kPT) void train_pass_kernel(TrainArgs a)
     const int c0 = kCW * wave;
     const int n = a.n;
     const int64_t kp = a.kpad;
-    const int64_t nblk = kp / 32;  // bias partials: slot-major, room for kpad / 32 blocks
+    const int64_t nblk = kp / 32;  // block stride of a slot group in dbp (room for 32-row blocks)
     const bf16x8 zero8 = {};
 
     // B fragments of a 256 x kCW slice whose column c has its K values

@@ -93,6 +93,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the one-core oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="headline line without the c3/c4/c5 sub-objects")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the FP64 fma and copy microbenchmarks")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first run one device-to-device copy of BYTES (the plain copy kernel that "
@@ -534,6 +535,16 @@ def main():
     if args.verbose:
         for i in r["last"]:
             print(json.dumps(i), file=sys.stderr)
+    if not args.no_peaks:
+        # context for the fractions above (which stay against the published
+        # peaks): what this device sustains on a plain FP64 fma loop and a copy
+        pk = A.measure_peaks(5)
+        out["measured_peaks"] = {"fp64_fma_tflops": round(pk["fp64_tflops"], 2),
+                                 "clock_mhz_during_fma": round(pk["clock_mhz"]),
+                                 "copy_gbs": round(pk["copy_gbs"], 1)}
+        for key in ("roofline", "roofline_other_kernel"):
+            if key in out and pk["fp64_tflops"] > 0:
+                out[key]["frac_of_measured_fp64"] = round(out[key]["achieved"] / pk["fp64_tflops"], 4)
     if units_1:
         out["cpu_baseline"] = cpu_baseline(w, r["last"], units_1, units_all)
         out["cpu_baseline"]["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]

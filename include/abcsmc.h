@@ -242,6 +242,18 @@ int abcsmc_simulate(const abcsmc_config* cfg, int64_t n, const double* theta, co
  *                                                out: double[n]) */
 int abcsmc_debug_eval(int32_t fn, int64_t n, const void* in, void* out, double param_a, int32_t param_b);
 
+/* Measurement helper (not part of the method): what the current device
+ * sustains, as context for the roofline fractions, which are taken against
+ * the published peaks.  fp64_tflops: FP64 vector fma throughput (2 flops per
+ * fma) of eight independent chains per lane at eight waves per SIMD;
+ * clock_mhz: the shader clock during that launch (its cycle counter against
+ * the 100 MHz constant counter); copy_gbs: device-to-device copy of 1 GiB
+ * (bytes read + bytes written per second).  Each the best of `repeats`
+ * (1..100) timed launches after one untimed one.  Allocates 2 GiB + 4 MiB of
+ * device memory for the duration of the call (ABCSMC_ENOMEM if it cannot);
+ * runs on the null stream of the current device and waits for it. */
+int abcsmc_measure_peaks(int32_t repeats, double* fp64_tflops, double* clock_mhz, double* copy_gbs);
+
 /* ---------------------------------------------------------------------------
  * Batched mode: many independent runs (own population, horizon, particle
  * count, seed, observations, step law) advanced one stage at a time by one

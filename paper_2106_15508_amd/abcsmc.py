@@ -30,7 +30,7 @@ F_SKIP_WEIGHTS = 4
 EXPORTS = (
     "abcsmc_workspace_size", "abcsmc_init", "abcsmc_round", "abcsmc_weights", "abcsmc_population",
     "abcsmc_resampling", "abcsmc_reset", "abcsmc_rounds_done", "abcsmc_snapshot", "abcsmc_restore",
-    "abcsmc_run", "abcsmc_simulate", "abcsmc_debug_eval",
+    "abcsmc_run", "abcsmc_simulate", "abcsmc_debug_eval", "abcsmc_measure_peaks",
     "abcsmc_free", "abcsmc_strerror", "abcsmc_last_error", "abcsmc_abi_version",
     "abcsmc_batch_workspace_size", "abcsmc_batch_init", "abcsmc_batch_set_schedule",
     "abcsmc_batch_get_schedule", "abcsmc_batch_autotune", "abcsmc_batch_round", "abcsmc_batch_run",
@@ -140,6 +140,7 @@ def load(path: Optional[str] = None):
         "abcsmc_run": (C.c_int, [vp, vp, i32, vp, vp, vp, vp]),
         "abcsmc_simulate": (C.c_int, [vp, i64, vp, vp, u64, u32, u32, vp]),
         "abcsmc_debug_eval": (C.c_int, [i32, i64, vp, vp, d, i32]),
+        "abcsmc_measure_peaks": (C.c_int, [i32, vp, vp, vp]),
         "abcsmc_free": (None, [vp]),
         "abcsmc_strerror": (C.c_char_p, [C.c_int]),
         "abcsmc_last_error": (C.c_char_p, [vp]),
@@ -257,6 +258,14 @@ def debug_eval(fn: int, inp: np.ndarray, n: int, out: np.ndarray, pa: float = 0.
     inp = np.ascontiguousarray(inp)
     _check(load().abcsmc_debug_eval(fn, n, _p(inp), _p(out), pa, pb))
     return out
+
+
+def measure_peaks(repeats: int = 3) -> dict:
+    """abcsmc_measure_peaks: what the current device sustains (FP64 fma
+    TFLOP/s, the shader clock in MHz during that launch, copy GB/s)."""
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    _check(load().abcsmc_measure_peaks(repeats, C.byref(a), C.byref(b), C.byref(c)))
+    return dict(fp64_tflops=a.value, clock_mhz=b.value, copy_gbs=c.value)
 
 
 class Context:

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libabcsmc_hip.so")
 SOURCES = ["sim.hip", "smc.hip", "sort.hip", "runtime.hip", "batch.hip", "batch_rt.hip", "mlp.hip", "train.hip", "screen.hip",
-           "surrogate_rt.hip", "predict.hip", "checkpoint.hip"]
+           "surrogate_rt.hip", "predict.hip", "checkpoint.hip", "peak.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -118,3 +118,12 @@ def test_null_arguments():
     assert L.abcsmc_round(None, None) == A.EINVAL
     assert L.abcsmc_weights(None, None, None, None) == A.EINVAL
     L.abcsmc_free(None)
+
+
+def test_measure_peaks_rejects_bad_arguments():
+    L = A.load()
+    x = C.c_double()
+    assert L.abcsmc_measure_peaks(0, C.byref(x), C.byref(x), C.byref(x)) == A.EINVAL
+    assert L.abcsmc_measure_peaks(101, C.byref(x), C.byref(x), C.byref(x)) == A.EINVAL
+    assert L.abcsmc_measure_peaks(3, None, C.byref(x), C.byref(x)) == A.EINVAL
+    assert b"measure_peaks" in L.abcsmc_last_error(None)

@@ -170,3 +170,15 @@ def test_weight_term_against_oracle(oracle):
           % (rel.max(), x[np.argmax(rel)], rel[w], x[w]), flush=True)
     assert ratio.max() <= 1.0, (rel[w], x[w])
     assert np.all(got[~big] < 1e-300) and np.all(got >= 0)
+
+
+def test_measured_peaks_are_plausible():
+    """The measurement helper behind bench.py's `measured_peaks`: an FP64 fma
+    loop cannot beat the published 78.6 TFLOP/s (at most 2.4 GHz), the clock
+    it reports lies in the device's range, and a copy cannot beat 8 TB/s."""
+    pk = A.measure_peaks(2)
+    assert 30.0 < pk["fp64_tflops"] <= 78.6 * 1.02
+    assert 1000.0 < pk["clock_mhz"] <= 2500.0
+    # the fma rate follows from the clock: 256 CUs x 64 lanes x 2 flops per cycle
+    assert pk["fp64_tflops"] <= 256 * 64 * 2 * pk["clock_mhz"] * 1e6 / 1e12 * 1.05
+    assert 1000.0 < pk["copy_gbs"] <= 8000.0 * 1.02

@@ -500,6 +500,10 @@ def main():
         if workers > 1:
             log(f"oracle on {workers} cores ...")
             units_all = cpu_unit_costs(w, args.cpu_seconds / 2, workers)
+    units_c3 = None
+    if not args.no_cpu_baseline and args.workload == "c2" and not args.no_extra:
+        log("oracle on one core, c3 sample ...")
+        units_c3 = cpu_unit_costs(W.C3, args.cpu_seconds / 2, 1)
 
     import torch
 
@@ -558,6 +562,9 @@ def main():
                      "simulations_per_s": s3["simulations_per_s"], "particle_days_per_s": s3["particle_days_per_s"],
                      "kernel_ms": s3["kernel_ms"], "weight_terms": s3["weight_terms"],
                      "roofline": s3["roofline"], "roofline_other_kernel": s3["roofline_other_kernel"]}
+        if units_c3:
+            out["c3"]["cpu_baseline"] = cpu_baseline(w3, r3["last"], units_c3, None)
+            out["c3"]["cpu_baseline"]["gpu_over_cpu"] = s3["value"] / out["c3"]["cpu_baseline"]["value"]
         log("c4: batched mode, 3 steps after 1 warm-up, then the runs one at a time")
         out["c4"] = bench_batched(args, min(args.steps, 3), 1)
         log("c5: learned screen, 1 step after 1 warm-up, beside the plain form")

@@ -138,6 +138,33 @@ def test_short_first_batch_completed_and_weights_redone(oracle):
     assert infos[2]["weight_terms"] <= wl.n_particles * infos[2]["survivors"]
 
 
+def _random_workload(k):
+    """Seeded draw of a small configuration: population, horizon, particle
+    count (ragged against the 256-lane workgroups), survival ratio and seeds
+    drawn; step law, sampler, the variance reading of the step and early
+    exit cycled so that the six draws cover each of them."""
+    rng = np.random.default_rng(9000 + k)
+    step = (W.STEP_PAPER, W.STEP_FIXED, W.STEP_MEANVAR, W.STEP_PAPER, W.STEP_MODECONC, W.STEP_FIXED)[k]
+    kw = dict(population=int(np.exp(rng.uniform(np.log(2e4), np.log(5e6)))), n_days=int(rng.integers(20, 91)),
+              n_particles=int(rng.choice([300, 517, 1024, 1500, 2048])), n_rounds=3,
+              surv_ratio=float(rng.choice([0.3, 0.5, 0.7])), sampler=k % 2, step_schedule=step,
+              seed=int(rng.integers(1, 1 << 30)), obs_seed=int(rng.integers(1, 1 << 30)),
+              step_is_variance=(k // 2) % 2 == 1)
+    if step == W.STEP_FIXED:
+        kw.update(beta_a=float(rng.uniform(0.5, 4.0)), beta_b=int(rng.integers(1, 9)))
+    return W.tiny(**kw), (A.F_EARLY_EXIT if k % 3 else 0)
+
+
+@pytest.mark.parametrize("k", range(6))
+def test_random_configurations_bitwise(oracle, k):
+    wl, flags = _random_workload(k)
+    obs = oracle.observations(wl)
+    ref = oracle.run(wl, obs)
+    assert ref.rc == 0, wl
+    infos, pops = _gpu_run(wl, obs, wl.n_rounds, flags=flags)
+    _compare_run(oracle, wl, ref, infos, pops, wl.n_rounds)
+
+
 def test_early_exit_keeps_acceptances(oracle):
     wl = W.tiny(n_rounds=3)
     obs = oracle.observations(wl)

@@ -104,6 +104,41 @@ def test_batched_equals_oracle(oracle_runs, flags, sched):
                 _same_as_oracle(b.population(r), infos[r], refs[r], s, (runs[r].name, s, flags))
 
 
+def _random_batch(k):
+    """Seeded draw of a batch of seven small runs: each run's population,
+    horizon, particle count (ragged), survival ratio, sampler, step law
+    (eq. 16 or a fixed Beta) and seeds drawn independently."""
+    rng = np.random.default_rng(7100 + k)
+    runs = []
+    for r in range(7):
+        kw = dict(name=f"r{k}_{r}", population=int(np.exp(rng.uniform(np.log(2e4), np.log(3e6)))),
+                  n_days=int(rng.integers(15, 80)), n_particles=int(rng.choice([256, 300, 640, 1111, 2048])),
+                  surv_ratio=float(rng.choice([0.3, 0.5, 0.7])), sampler=int(rng.integers(0, 2)),
+                  seed=int(rng.integers(1, 1 << 30)), obs_seed=int(rng.integers(1, 1 << 30)),
+                  step_is_variance=bool(rng.integers(0, 2)))
+        if rng.integers(0, 2):
+            kw.update(step_schedule=W.STEP_FIXED, beta_a=float(rng.uniform(0.5, 4.0)),
+                      beta_b=int(rng.integers(1, 9)))
+        runs.append(W.tiny(**kw))
+    return runs
+
+
+@pytest.mark.parametrize("k", range(2))
+def test_random_batches_equal_oracle(oracle, k):
+    """Two seeded batches of seven runs each, three stages, early exit on:
+    every run against the oracle's run stage by stage."""
+    runs = _random_batch(k)
+    obs = [oracle.observations(w) for w in runs]
+    refs = [oracle.run(w, o, n_rounds=3) for w, o in zip(runs, obs)]
+    assert all(r.rc == 0 for r in refs)
+    with A.Batch(runs, obs, flags=A.F_EARLY_EXIT) as b:
+        for s in range(3):
+            infos = b.round()
+            for r in range(len(runs)):
+                assert b.status(r) == A.OK
+                _same_as_oracle(b.population(r), infos[r], refs[r], s, (runs[r].name, s))
+
+
 @pytest.mark.parametrize("flags", [0, A.F_EARLY_EXIT])
 def test_batched_equals_plain(oracle, flags):
     runs = _runs()

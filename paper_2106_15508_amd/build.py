@@ -51,7 +51,26 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    build_demo(verbose)
     return LIB
+
+
+DEMO_SRC = os.path.join(HERE, "examples", "abcsmc_demo.c")
+DEMO = os.path.join(HERE, "examples", "abcsmc_demo")
+
+
+def build_demo(verbose: bool = False) -> str:
+    """The plain-C example program, linked against the library built above
+    (found next to it at run time)."""
+    cc = shutil.which("cc") or shutil.which("gcc")
+    if cc is None:
+        raise RuntimeError("no C compiler for the example program")
+    cmd = [cc, "-std=c99", "-O2", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"), DEMO_SRC,
+           "-L", HERE, "-labcsmc_hip", "-Wl,-rpath,$ORIGIN/..", "-lm", "-o", DEMO]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    return DEMO
 
 
 if __name__ == "__main__":

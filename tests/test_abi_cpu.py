@@ -127,3 +127,15 @@ def test_measure_peaks_rejects_bad_arguments():
     assert L.abcsmc_measure_peaks(101, C.byref(x), C.byref(x), C.byref(x)) == A.EINVAL
     assert L.abcsmc_measure_peaks(3, None, C.byref(x), C.byref(x)) == A.EINVAL
     assert b"measure_peaks" in L.abcsmc_last_error(None)
+
+
+def test_c_example_compiles_against_the_header(tmp_path):
+    """The plain-C example builds with -std=c99 -Wall -Wextra -Werror against
+    include/abcsmc.h and links against the library (no GPU needed)."""
+    import subprocess
+    from paper_2106_15508_amd import build as B
+    out = tmp_path / "demo"
+    cmd = ["cc", "-std=c99", "-O1", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"), B.DEMO_SRC,
+           "-L", B.HERE, "-labcsmc_hip", "-lm", "-o", str(out)]
+    subprocess.run(cmd, check=True, capture_output=True, timeout=120)
+    assert out.exists()

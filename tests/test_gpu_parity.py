@@ -286,6 +286,10 @@ def test_alternative_beta_parameterisations_bitwise(oracle, wl):
            n_rounds=3, seed=22),
     # tiny survival ratio (eq. 8 at the 2nd order statistic) and N not a multiple of a wave
     W.tiny(n_particles=97, surv_ratio=0.01, n_rounds=4, seed=23),
+    # the longest horizon the library accepts (4096 days)
+    W.tiny(n_particles=64, n_days=4096, n_rounds=3, seed=24),
+    # a population of 2^52: counts near the top of the exact-integer range of doubles
+    W.tiny(population=1 << 52, n_days=40, n_rounds=3, seed=25),
 ])
 def test_edge_configurations_bitwise(oracle, wl):
     obs = oracle.observations(wl)
